@@ -1,0 +1,149 @@
+/*
+ * sphere_poisson.h -- C ABI of the MI355X (gfx950) DFS spectral Poisson solver.
+ *
+ * Method: Townsend, Wilber & Wright, "Computing with functions in spherical and
+ * polar geometries I. The sphere", Section 5 ("A fast and optimal spectral
+ * method for Poisson's equation").  Given samples of f on the sphere the
+ * library returns samples of u with
+ *
+ *     sin^2(theta) u_thth + cos(theta) sin(theta) u_th + u_lamlam = sin^2(theta) f
+ *
+ * (eq. SphericalLaplacian) together with the integral constraint
+ * int_0^pi int_-pi^pi u sin(theta) dlambda dtheta = integral
+ * (eq. integralConstraint2; the paper fixes integral = 0).  The discretisation
+ * is the double Fourier sphere (Section 2.2, eq. BMCsphere) with the Fourier
+ * spectral method of Section 5: one banded system per lambda-wavenumber k
+ * (eq. linearSystems, solved with the k^2 term subtracted), the k = 0 system
+ * bordered by the integration weights of Section 4 (eq. integrationCoeffs,
+ * eq. pentdiagonalPlusRankOne).
+ *
+ * GRID AND LAYOUT (all entry points)
+ *   f, u, g, fbar are device pointers to contiguous row-major [m][n] float64
+ *   arrays: element (j, i) at offset j*n + i holds the value at
+ *       theta_j  = (j + 1/2) * pi / m      (colatitude, j = 0..m-1, poles excluded)
+ *       lambda_i = -pi + 2 * pi * i / n    (azimuth,    i = 0..n-1).
+ *   n must be even (the doubling needs lambda + pi on the grid), n >= 4,
+ *   m >= 4.  Every prime factor of n/2 and of m must be <= 31.
+ *   Inputs and outputs must not overlap (SP_ERR_ALIAS otherwise).
+ *
+ * OWNERSHIP AND STREAMS
+ *   The caller owns every f/u/g/fbar buffer and the stream.  A plan owns all
+ *   device workspace, twiddle tables and launch schedules; it is created once
+ *   (this allocates) and may be reused for any number of solves.  Solve calls
+ *   allocate nothing, enqueue their kernels on `hip_stream` (a hipStream_t;
+ *   NULL = the legacy default stream) and return without waiting, unless
+ *   SP_SYNC_INFO is set.  A plan must not be used by two streams at once
+ *   (its workspace is shared by consecutive calls).
+ *
+ * ERRORS
+ *   Every function returns an sp_status; nothing is printed, thrown or
+ *   aborted across this boundary.  sphere_poisson_strerror() returns a static
+ *   string (for SP_ERR_HIP it includes the last HIP error text of the calling
+ *   thread).
+ */
+#ifndef SPHERE_POISSON_H
+#define SPHERE_POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SP_OK = 0,
+    SP_ERR_INVALID_ARG = 1,      /* null pointer, odd or too small n, m < 4, count <= 0, bad flags */
+    SP_ERR_UNSUPPORTED_SIZE = 2, /* a prime factor of n/2 or m exceeds 31, or a size exceeds 2^20 */
+    SP_ERR_OOM = 3,              /* device allocation failed while planning */
+    SP_ERR_HIP = 4,              /* a HIP runtime call failed (see strerror) */
+    SP_ERR_NOT_CONVERGED = 5,    /* MIXED: the correction did not fall below tol; u holds the last iterate */
+    SP_ERR_ALIAS = 6,            /* input and output buffers overlap */
+    SP_ERR_NO_DEVICE = 7,        /* no HIP device, or the current device is not gfx950 */
+    SP_ERR_BAD_PLAN = 8          /* null or destroyed plan */
+} sp_status;
+
+typedef enum {
+    SP_FP64 = 0,   /* every transform and solve in float64 */
+    SP_MIXED = 1   /* float32 transforms and banded solves, float64 residual, update and k = 0 system */
+} sp_precision;
+
+/* flags */
+#define SP_SYNC_INFO 0x1u   /* the solve synchronises `hip_stream` and fills *info (norms computed on device) */
+
+typedef struct {
+    int n_lambda;       /* n: samples in lambda (even, >= 4) */
+    int m_theta;        /* m: samples in theta (>= 4) */
+    int precision;      /* sp_precision */
+    int max_refine;     /* MIXED: number of iterative-refinement corrections (>= 0; 1 is enough for 1e-10) */
+    double tol;         /* MIXED with SP_SYNC_INFO: required ||last correction|| / ||u|| (<= 0: no check) */
+    unsigned flags;     /* SP_SYNC_INFO */
+} sp_desc;
+
+typedef struct {
+    int iters;               /* refinement corrections applied (0 for FP64) */
+    double rel_correction;   /* ||last correction||_2 / ||u||_2 (MIXED), 0 for FP64 */
+    double f_integral;       /* quadrature of int f sin(theta) dtheta dlambda (exact for band-limited f) */
+    int status;              /* sp_status of the call */
+} sp_info;
+
+typedef struct sp_plan_s* sp_plan;
+
+/* Create a plan for one (n, m, precision).  Validates sizes, factorises n/2
+ * and m into radices <= 31, computes float64 twiddle tables on the host
+ * (exact-angle reduction) and uploads them, allocates the spectrum workspace
+ * (about 8 bytes per grid point for SP_FP64, 24 for SP_MIXED) and picks the
+ * launch schedule.  `hip_stream` is used for the uploads.
+ * Errors: SP_ERR_INVALID_ARG, SP_ERR_UNSUPPORTED_SIZE, SP_ERR_OOM, SP_ERR_HIP,
+ * SP_ERR_NO_DEVICE.  On error *out is set to NULL. */
+int sphere_poisson_plan(sp_plan* out, const sp_desc* desc, void* hip_stream);
+
+/* Solve the Poisson problem of Section 5 for one right-hand side:
+ * f (input, device, [m][n] float64), u (output, device, [m][n] float64),
+ * `integral` = prescribed value of the integral of u sin(theta) over the
+ * doubled-up half domain (the constraint row of the k = 0 system).
+ * f is not required to have zero mean (the paper's precondition); the
+ * bordered k = 0 system is solved as is and info->f_integral reports the
+ * mean.  `info` may be NULL; it is filled only with SP_SYNC_INFO.
+ * Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG, SP_ERR_ALIAS, SP_ERR_HIP,
+ * SP_ERR_NOT_CONVERGED (MIXED, SP_SYNC_INFO and tol > 0 only). */
+int sphere_poisson_solve(sp_plan plan, const double* f, double* u, double integral,
+                         void* hip_stream, sp_info* info);
+
+/* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
+ * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
+ * for any loss; same layout, ownership and errors as sphere_poisson_solve. */
+int sphere_poisson_solve_adjoint(sp_plan plan, const double* g, double* fbar,
+                                 void* hip_stream, sp_info* info);
+
+/* Solve `count` independent problems of possibly different sizes in one
+ * persistent launch captured in a HIP graph.  n[r], m[r]: sizes of problem r
+ * (host arrays); f[r], u[r]: device pointers (host arrays of pointers).
+ * The batch plan (workspace, schedules per distinct size, graph) is built on
+ * the first call for a given size list and reused while the list and the
+ * pointers are unchanged.  `infos` may be NULL (else `count` entries).
+ * Errors: as sphere_poisson_plan and sphere_poisson_solve. */
+int sphere_poisson_solve_batch(int count, const int* n, const int* m,
+                               const double* const* f, double* const* u,
+                               int precision, void* hip_stream, sp_info* infos);
+
+/* Release every resource of a plan (waits for its pending work). */
+int sphere_poisson_destroy(sp_plan plan);
+
+/* Human-readable text for a status code (static storage). */
+const char* sphere_poisson_strerror(int code);
+
+/* Bytes of device workspace a plan for `desc` would allocate (0 on invalid desc). */
+size_t sphere_poisson_workspace_bytes(const sp_desc* desc);
+
+/* Diagnostic: the transform pipeline without the solve.  Returns, for every
+ * sample, the value obtained by the forward lambda/theta transforms of
+ * sin^2(theta) f followed by the inverse transforms (identity up to rounding
+ * on sin^2(theta) f).  Used to test the transforms in isolation. */
+int sphere_poisson_transform_roundtrip(sp_plan plan, const double* f, double* out,
+                                       void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPHERE_POISSON_H */

@@ -1,0 +1,204 @@
+"""Python binding of the MI355X DFS spectral Poisson solver (C ABI in
+include/sphere_poisson.h).  Argument marshalling only: every step of the
+solve runs in the HIP library; torch provides device memory and the stream.
+
+The solver follows Townsend, Wilber & Wright, Section 5: samples f[j, i] at
+theta_j = (j + 1/2) pi / m, lambda_i = -pi + 2 pi i / n (float64, [m, n])
+give samples u of the solution of the sin^2-scaled Poisson equation on the
+unit sphere with a prescribed integral of u.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # loads the HIP runtime that the library then shares
+
+__all__ = ["SpherePoisson", "SpherePoissonFunction", "solve_batch", "library", "LibraryMissing",
+           "SP_FP64", "SP_MIXED", "SP_SYNC_INFO", "SpError", "exported_symbols"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsphere_poisson.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "sphere_poisson.h")
+
+SP_FP64, SP_MIXED = 0, 1
+SP_SYNC_INFO = 0x1
+_STATUS = {0: "SP_OK", 1: "SP_ERR_INVALID_ARG", 2: "SP_ERR_UNSUPPORTED_SIZE", 3: "SP_ERR_OOM",
+           4: "SP_ERR_HIP", 5: "SP_ERR_NOT_CONVERGED", 6: "SP_ERR_ALIAS", 7: "SP_ERR_NO_DEVICE",
+           8: "SP_ERR_BAD_PLAN"}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class SpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class SpDesc(ctypes.Structure):
+    _fields_ = [("n_lambda", ctypes.c_int), ("m_theta", ctypes.c_int), ("precision", ctypes.c_int),
+                ("max_refine", ctypes.c_int), ("tol", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
+class SpInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_correction", ctypes.c_double),
+                ("f_integral", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+_lib = None
+
+
+def exported_symbols() -> list[str]:
+    """Function names declared in the C header."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return re.findall(r"^\s*(?:int|const char\*|size_t)\s+(sphere_poisson_\w+)\s*\(", text, re.M)
+
+
+def library():
+    """Load the in-tree HIP library (raises LibraryMissing if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing("HIP library %s is not built; run `python -m paper_1510_08094_amd.build`"
+                             % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.sphere_poisson_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SpDesc), vp]
+    lib.sphere_poisson_solve.argtypes = [vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_solve_adjoint.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_solve_batch.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
+                                               ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp,
+                                               ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_destroy.argtypes = [vp]
+    lib.sphere_poisson_strerror.argtypes = [ci]
+    lib.sphere_poisson_strerror.restype = ctypes.c_char_p
+    lib.sphere_poisson_workspace_bytes.argtypes = [ctypes.POINTER(SpDesc)]
+    lib.sphere_poisson_workspace_bytes.restype = ctypes.c_size_t
+    lib.sphere_poisson_transform_roundtrip.argtypes = [vp, vp, vp, vp]
+    for name in ("sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
+                 "sphere_poisson_solve_batch", "sphere_poisson_destroy",
+                 "sphere_poisson_transform_roundtrip"):
+        getattr(lib, name).restype = ci
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise SpError(code, library().sphere_poisson_strerror(code).decode())
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_grid(t: torch.Tensor, m: int, n: int, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if tuple(t.shape) != (m, n):
+        raise ValueError("%s must have shape (m, n) = (%d, %d), got %s" % (name, m, n, tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+class SpherePoisson:
+    """A plan for one grid size and precision (owns the device workspace)."""
+
+    def __init__(self, n: int, m: int, precision: str = "fp64", max_refine: int = 1, tol: float = 0.0,
+                 sync_info: bool = False, device=None):
+        lib = library()
+        self.n, self.m = int(n), int(m)
+        self.precision = {"fp64": SP_FP64, "mixed": SP_MIXED}[precision]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.desc = SpDesc(self.n, self.m, self.precision, int(max_refine), float(tol),
+                           SP_SYNC_INFO if sync_info else 0)
+        self._plan = ctypes.c_void_p()
+        self.info = SpInfo()
+        with torch.cuda.device(self.device):
+            _check(lib.sphere_poisson_plan(ctypes.byref(self._plan), ctypes.byref(self.desc),
+                                           ctypes.c_void_p(_stream_handle(self.device))))
+
+    def solve(self, f: torch.Tensor, integral: float = 0.0, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_grid(f, self.m, self.n, "f")
+        u = torch.empty_like(f) if out is None else out
+        _check_grid(u, self.m, self.n, "out")
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_solve(self._plan, ctypes.c_void_p(f.data_ptr()),
+                                                  ctypes.c_void_p(u.data_ptr()), float(integral),
+                                                  ctypes.c_void_p(_stream_handle(self.device)),
+                                                  ctypes.byref(self.info)))
+        return u
+
+    def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_grid(g, self.m, self.n, "g")
+        fb = torch.empty_like(g) if out is None else out
+        _check_grid(fb, self.m, self.n, "out")
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_solve_adjoint(self._plan, ctypes.c_void_p(g.data_ptr()),
+                                                          ctypes.c_void_p(fb.data_ptr()),
+                                                          ctypes.c_void_p(_stream_handle(self.device)),
+                                                          ctypes.byref(self.info)))
+        return fb
+
+    def roundtrip(self, f: torch.Tensor) -> torch.Tensor:
+        _check_grid(f, self.m, self.n, "f")
+        out = torch.empty_like(f)
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_transform_roundtrip(
+                self._plan, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                ctypes.c_void_p(_stream_handle(self.device))))
+        return out
+
+    def close(self):
+        if self._plan:
+            _check(library().sphere_poisson_destroy(self._plan))
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SpherePoissonFunction(torch.autograd.Function):
+    """u = S f with the hand-written adjoint as the backward pass."""
+
+    @staticmethod
+    def forward(ctx, f: torch.Tensor, plan: SpherePoisson) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.solve(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.adjoint(g.contiguous()), None
+
+
+def solve_batch(fs, precision: str = "mixed", outs=None):
+    """Solve every f in `fs` (list of [m_r, n_r] float64 CUDA tensors) in one call."""
+    lib = library()
+    count = len(fs)
+    ns = (ctypes.c_int * count)(*[int(f.shape[1]) for f in fs])
+    ms = (ctypes.c_int * count)(*[int(f.shape[0]) for f in fs])
+    us = [torch.empty_like(f) for f in fs] if outs is None else outs
+    for f, u in zip(fs, us):
+        _check_grid(f, f.shape[0], f.shape[1], "f")
+        _check_grid(u, f.shape[0], f.shape[1], "out")
+    fp = (ctypes.c_void_p * count)(*[f.data_ptr() for f in fs])
+    up = (ctypes.c_void_p * count)(*[u.data_ptr() for u in us])
+    infos = (SpInfo * count)()
+    dev = fs[0].device
+    with torch.cuda.device(dev):
+        _check(lib.sphere_poisson_solve_batch(count, ns, ms, fp, up,
+                                              {"fp64": SP_FP64, "mixed": SP_MIXED}[precision],
+                                              ctypes.c_void_p(_stream_handle(dev)), infos))
+    return us

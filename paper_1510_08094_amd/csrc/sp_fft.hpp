@@ -1,0 +1,323 @@
+// Device building blocks: complex arithmetic, compile-time roots of unity,
+// radix-R DFT codelets held in registers, and one Stockham autosort pass over
+// a line held in LDS.  Used by the lambda and theta transform kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sp {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct alignas(2 * sizeof(T)) Cx {
+    T x, y;
+};
+
+template <typename T> __device__ __forceinline__ Cx<T> cmake(T a, T b) { return Cx<T>{a, b}; }
+template <typename T> __device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> operator*(Cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T> __device__ __forceinline__ Cx<T> cconj(Cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ Cx<T> mul_i(Cx<T> a) { return {-a.y, a.x}; }      // i * a
+template <typename T> __device__ __forceinline__ Cx<T> mul_negi(Cx<T> a) { return {a.y, -a.x}; }  // -i * a
+
+// ---------------------------------------------------------------- constants
+// cos / sin of 2 pi num / den evaluated at compile time: exact octant
+// reduction in integers, then Taylor series on [0, pi/4] summed from the
+// smallest term (about one ulp).
+namespace ct {
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+    double t[16] = {};
+    double term = x;
+    t[0] = x;
+    for (int k = 1; k < 16; ++k) {
+        term = term * (-(x * x)) / double((2 * k) * (2 * k + 1));
+        t[k] = term;
+    }
+    double s = 0.0;
+    for (int k = 15; k >= 0; --k) s += t[k];
+    return s;
+}
+
+constexpr double taylor_cos(double x) {
+    double t[16] = {};
+    double term = 1.0;
+    t[0] = 1.0;
+    for (int k = 1; k < 16; ++k) {
+        term = term * (-(x * x)) / double((2 * k - 1) * (2 * k));
+        t[k] = term;
+    }
+    double s = 0.0;
+    for (int k = 15; k >= 0; --k) s += t[k];
+    return s;
+}
+
+struct CS { double c, s; };
+
+constexpr CS cossin2pi(long long num, long long den) {
+    long long t = num % den;
+    if (t < 0) t += den;
+    long long a = 8 * t;
+    long long o = a / den;         // octant 0..7
+    long long r = a - o * den;     // angle = (o + r/den) * pi/4
+    double x = (double)r / (double)den * (kPi / 4.0);
+    double y = (double)(den - r) / (double)den * (kPi / 4.0);
+    double cx = taylor_cos(x), sx = taylor_sin(x), cy = taylor_cos(y), sy = taylor_sin(y);
+    if (r == 0) { cx = 1.0; sx = 0.0; cy = 0.0; sy = 0.0; }
+    switch (o) {
+        case 0: return {cx, sx};
+        case 1: return r == 0 ? CS{0.70710678118654752440, 0.70710678118654752440} : CS{sy, cy};
+        case 2: return r == 0 ? CS{0.0, 1.0} : CS{-sx, cx};
+        case 3: return r == 0 ? CS{-0.70710678118654752440, 0.70710678118654752440} : CS{-cy, sy};
+        case 4: return r == 0 ? CS{-1.0, 0.0} : CS{-cx, -sx};
+        case 5: return r == 0 ? CS{-0.70710678118654752440, -0.70710678118654752440} : CS{-sy, -cy};
+        case 6: return r == 0 ? CS{0.0, -1.0} : CS{sx, -cx};
+        default: return r == 0 ? CS{0.70710678118654752440, -0.70710678118654752440} : CS{cy, -sy};
+    }
+}
+
+template <int R>
+struct Roots {
+    double c[R];
+    double s[R];
+    constexpr Roots() : c(), s() {
+        for (int t = 0; t < R; ++t) {
+            CS v = cossin2pi(t, R);
+            c[t] = v.c;
+            s[t] = v.s;
+        }
+    }
+};
+}  // namespace ct
+
+// ---------------------------------------------------------------- codelets
+// Forward DFT: X_k = sum_j x_j e^{-2 pi i jk/R}; inverse uses e^{+...}
+// (unnormalised).  In place on v[0..R-1].
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(Cx<T>& a, Cx<T>& b) {
+    Cx<T> t = a - b;
+    a = a + b;
+    b = t;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(Cx<T>& a0, Cx<T>& a1, Cx<T>& a2, Cx<T>& a3) {
+    Cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3;
+    Cx<T> t3 = INV ? mul_i(a1 - a3) : mul_negi(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(Cx<T>* v) {
+    constexpr T r2 = (T)0.70710678118654752440;
+    Cx<T> a0 = v[0] + v[4], a4 = v[0] - v[4];
+    Cx<T> a1 = v[1] + v[5], a5 = v[1] - v[5];
+    Cx<T> a2 = v[2] + v[6], a6 = v[2] - v[6];
+    Cx<T> a3 = v[3] + v[7], a7 = v[3] - v[7];
+    if (!INV) {
+        a5 = Cx<T>{(a5.x + a5.y) * r2, (a5.y - a5.x) * r2};     // * e^{-i pi/4}
+        a6 = mul_negi(a6);                                      // * -i
+        a7 = Cx<T>{(a7.y - a7.x) * r2, -(a7.x + a7.y) * r2};    // * e^{-3 i pi/4}
+    } else {
+        a5 = Cx<T>{(a5.x - a5.y) * r2, (a5.x + a5.y) * r2};
+        a6 = mul_i(a6);
+        a7 = Cx<T>{-(a7.x + a7.y) * r2, (a7.x - a7.y) * r2};
+    }
+    dft4<T, INV>(a0, a1, a2, a3);
+    dft4<T, INV>(a4, a5, a6, a7);
+    v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+    v[1] = a4; v[3] = a5; v[5] = a6; v[7] = a7;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(Cx<T>* v) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle w16^{n2 k1}, DFT4 over n2
+    constexpr ct::Roots<16> W{};
+    Cx<T> y[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        Cx<T> a = v[n2], b = v[4 + n2], c = v[8 + n2], d = v[12 + n2];
+        dft4<T, INV>(a, b, c, d);
+        y[n2 * 4 + 0] = a; y[n2 * 4 + 1] = b; y[n2 * 4 + 2] = c; y[n2 * 4 + 3] = d;
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) {
+            const int t = n2 * k1;
+            Cx<T> w{(T)W.c[t], INV ? (T)W.s[t] : (T)(-W.s[t])};
+            y[n2 * 4 + k1] = cmul(y[n2 * 4 + k1], w);
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        Cx<T> a = y[0 * 4 + k1], b = y[1 * 4 + k1], c = y[2 * 4 + k1], d = y[3 * 4 + k1];
+        dft4<T, INV>(a, b, c, d);
+        v[k1 + 0] = a; v[k1 + 4] = b; v[k1 + 8] = c; v[k1 + 12] = d;
+    }
+}
+
+// Odd R: pair the inputs j and R-j; X_r = x0 + sum_j (x_j + x_{R-j}) cos(2 pi rj/R)
+//                                         -/+ i sum_j (x_j - x_{R-j}) sin(2 pi rj/R)
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_odd(Cx<T>* v) {
+    constexpr int H = (R - 1) / 2;
+    constexpr ct::Roots<R> W{};
+    Cx<T> s[H], d[H];
+    Cx<T> x0 = v[0];
+    Cx<T> sum = x0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        s[j - 1] = v[j] + v[R - j];
+        d[j - 1] = v[j] - v[R - j];
+        sum = sum + s[j - 1];
+    }
+    v[0] = sum;
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+        Cx<T> A = x0, B{(T)0, (T)0};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int t = (r * j) % R;
+            A = A + s[j - 1] * (T)W.c[t];
+            B = B + d[j - 1] * (T)W.s[t];
+        }
+        // forward: X_r = A - iB, X_{R-r} = A + iB
+        Cx<T> iB = mul_i(B);
+        v[r] = INV ? A + iB : A - iB;
+        v[R - r] = INV ? A - iB : A + iB;
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(Cx<T>* v) {
+    if constexpr (R == 2) {
+        dft2<T, INV>(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        dft8<T, INV>(v);
+    } else if constexpr (R == 16) {
+        dft16<T, INV>(v);
+    } else {
+        static_assert(R % 2 == 1, "unsupported radix");
+        dft_odd<T, R, INV>(v);
+    }
+}
+
+// ---------------------------------------------------------------- plans
+constexpr int kMaxPass = 16;
+
+struct FftDesc {
+    int N;                 // transform length
+    int npass;
+    int radix[kMaxPass];
+    int tw_stride;         // tw[t * tw_stride] = e^{-2 pi i t / N}
+};
+
+// Butterflies each thread owns in a radix-R pass when a thread holds at most
+// EPT complex values in registers.
+template <int R, int EPT>
+struct Bpt {
+    static constexpr int value = (EPT / R) > 0 ? (EPT / R) : 1;
+};
+
+// One Stockham pass (radix R) over buf[0..N) in LDS, threads t in [0, nthr)
+// of this line.  Every thread of the workgroup must call it (it contains
+// barriers); `active` = false makes a thread only take part in the barriers.
+// Ns = product of the radices of the previous passes.
+//   butterfly j (0 <= j < N/R), k = j mod Ns:
+//     v_r = buf[j + r N/R] * w^{r k},  w = e^{-+2 pi i / (Ns R)}
+//     V = DFT_R(v);  buf[(j - k) R + k + r Ns] = V_r
+template <typename T, int R, bool INV, int EPT>
+__device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, int Ns,
+                                              const Cx<T>* __restrict__ tw, int tw_stride,
+                                              int t, int nthr, bool active) {
+    constexpr int B = Bpt<R, EPT>::value;
+    const int nb = N / R;
+    Cx<T> v[B][R];
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * nthr;
+            if (j < nb) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * nb];
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        const int span = N / (Ns * R);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * nthr;
+            if (j < nb) {
+                const int k = j % Ns;
+                if (k != 0) {
+                    const int step = span * k * tw_stride;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        const Cx<T> w = tw[r * step];
+                        v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+                    }
+                }
+                dft<T, R, INV>(v[b]);
+                const int base = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
+// radices compiled into this instantiation.
+template <typename T, bool INV, int EPT, int RMAX>
+__device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ buf, const FftDesc& d,
+                                        const Cx<T>* __restrict__ tw, int t, int nthr, bool active) {
+    int Ns = 1;
+    for (int p = 0; p < d.npass; ++p) {
+        const int R = d.radix[p];
+        switch (R) {
+            case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 4: stockham_pass<T, 4, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 5: stockham_pass<T, 5, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 7: stockham_pass<T, 7, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 8: stockham_pass<T, 8, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 11: stockham_pass<T, 11, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 13: stockham_pass<T, 13, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 16: stockham_pass<T, 16, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            default:
+                if constexpr (RMAX >= 17) {
+                    switch (R) {
+                        case 17: stockham_pass<T, 17, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        case 19: stockham_pass<T, 19, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        case 23: stockham_pass<T, 23, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        case 29: stockham_pass<T, 29, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        case 31: stockham_pass<T, 31, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        default: break;
+                    }
+                }
+                break;
+        }
+        Ns *= R;
+    }
+}
+
+}  // namespace sp

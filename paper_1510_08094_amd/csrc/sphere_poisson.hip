@@ -1,0 +1,596 @@
+// Host runtime and C ABI of the DFS spectral Poisson solver (see
+// include/sphere_poisson.h).  Plans own every device buffer; solves only
+// enqueue kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/sphere_poisson.h"
+#include "sp_kernels.hpp"
+
+using sp::Cx;
+using sp::FftDesc;
+
+namespace {
+
+thread_local std::string g_hip_err;
+
+int hip_fail(hipError_t e, const char* what) {
+    g_hip_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SP_ERR_HIP;
+}
+
+#define SP_HIP(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+    } while (0)
+
+constexpr int kEPT = 16;
+constexpr int kSmaxD = 12;   // chunk rows per thread, float64 solves
+constexpr int kSmaxF = 16;   // chunk rows per thread, float32 solves
+
+// ------------------------------------------------------------ twiddles
+// (cos, -sin)(2 pi t / N) in extended precision with exact quadrant
+// reduction of the angle; rounded once to double.
+void cis_neg(long long t, long long N, double* re, double* im) {
+    t %= N;
+    if (t < 0) t += N;
+    long long a = 4 * t;
+    long long qd = a / N;            // quadrant
+    long long r = a - qd * N;        // angle = (qd + r/N) * pi/2
+    long double x = (long double)r / (long double)N * (3.141592653589793238462643383279502884L / 2.0L);
+    long double c = cosl(x), s = sinl(x);
+    if (r == 0) { c = 1.0L; s = 0.0L; }
+    long double cc, ss;
+    switch (qd) {
+        case 0: cc = c; ss = s; break;
+        case 1: cc = -s; ss = c; break;
+        case 2: cc = -c; ss = -s; break;
+        default: cc = s; ss = -c; break;
+    }
+    *re = (double)cc;
+    *im = (double)(-ss);
+}
+
+// ------------------------------------------------------------ FFT planning
+bool factorize(int L, std::vector<int>& radices) {
+    radices.clear();
+    if (L < 1) return false;
+    int e = 0;
+    while (L % 2 == 0) { L /= 2; ++e; }
+    std::vector<int> p2;
+    while (e >= 3) { p2.push_back(8); e -= 3; }
+    if (e == 2) p2.push_back(4);
+    if (e == 1) {
+        if (!p2.empty()) p2[0] = 16;
+        else p2.push_back(2);
+    }
+    radices = p2;
+    static const int odd[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+    for (int p : odd) {
+        while (L % p == 0) { radices.push_back(p); L /= p; }
+    }
+    return L == 1 && (int)radices.size() <= sp::kMaxPass;
+}
+
+int bpt(int R) { return std::max(1, kEPT / R); }
+
+int fft_threads(const std::vector<int>& rad, int L) {
+    int t = 1;
+    for (int R : rad) t = std::max(t, ((L / R) + bpt(R) - 1) / bpt(R));
+    return t;
+}
+
+FftDesc make_desc(const std::vector<int>& rad, int L, int tw_stride) {
+    FftDesc d{};
+    d.N = L;
+    d.npass = (int)rad.size();
+    for (size_t i = 0; i < rad.size(); ++i) d.radix[i] = rad[i];
+    d.tw_stride = tw_stride;
+    return d;
+}
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+int round_up(int a, int b) { return ceil_div(a, b) * b; }
+
+struct ClassCounts { int ncA, ncB; };
+ClassCounts classes(int m, bool sine, bool k0) {
+    int qhi = sine ? m : m - 1;
+    int qA = k0 ? 2 : (sine ? 2 : 0);
+    ClassCounts c;
+    c.ncA = qhi >= qA ? (qhi - qA) / 2 + 1 : 0;
+    c.ncB = qhi >= 1 ? (qhi - 1) / 2 + 1 : 0;
+    return c;
+}
+
+int solve_threads(int m, int smax) {
+    int best = 0;
+    for (int s = 0; s < 2; ++s)
+        for (int z = 0; z < 2; ++z) {
+            if (s && z) continue;
+            ClassCounts c = classes(m, s, z);
+            best = std::max(best, ceil_div(c.ncA, smax) + ceil_div(c.ncB, smax));
+        }
+    return best;
+}
+
+// ------------------------------------------------------------ kernel table
+template <typename T>
+struct KernelSet {
+    void (*fwd)(sp::LambdaArgs<T>);
+    void (*inv)(sp::LambdaArgs<T>);
+    void (*theta)(sp::ThetaArgs<T>);
+};
+
+template <typename T, int RMAX>
+KernelSet<T> kernel_set() {
+    constexpr int SM = std::is_same<T, double>::value ? kSmaxD : kSmaxF;
+    return KernelSet<T>{&sp::k_lambda_fwd<T, kEPT, RMAX>, &sp::k_lambda_inv<T, kEPT, RMAX>,
+                        &sp::k_theta<T, kEPT, RMAX, SM>};
+}
+
+template <typename T>
+KernelSet<T> pick_kernels(int rmax) {
+    return rmax <= 16 ? kernel_set<T, 16>() : kernel_set<T, 32>();
+}
+
+template <typename T>
+struct Tables {
+    Cx<T>* tw_n = nullptr;   // n entries
+    Cx<T>* tw_m = nullptr;   // m entries
+    Cx<T>* eq = nullptr;     // m entries
+};
+
+}  // namespace
+
+// ------------------------------------------------------------ plan
+struct sp_plan_s {
+    sp_desc desc{};
+    int device = 0;
+    int n = 0, m = 0, N = 0;
+    int rw_log2 = 0;
+    int lam_threads = 0;      // threads per row in the lambda kernels
+    int theta_threads = 0;    // block size of the theta kernel
+    int theta_fft_threads = 0;
+    size_t lam_lds = 0, theta_lds64 = 0, theta_lds32 = 0;
+    int k8 = 0;
+    int rmax = 0;
+    FftDesc fft_lam{}, fft_theta{};
+    KernelSet<double> kd{};
+    KernelSet<float> kf{};
+    // device memory
+    void* block = nullptr;    // one allocation holding everything below
+    size_t block_bytes = 0;
+    Cx<double>* spec64 = nullptr;
+    Tables<double> t64;
+    Tables<float> t32;
+    double* sin2 = nullptr;
+    double* k0tab = nullptr;
+    double* fint_w = nullptr;
+    double* scal = nullptr;   // device scalars: [0] = integral of f
+    size_t spec_elems = 0;
+};
+
+namespace {
+
+std::mutex g_plans_mu;
+std::set<sp_plan> g_plans;   // live plans: a destroyed or foreign handle is rejected without a dereference
+
+bool plan_ok(sp_plan p) {
+    if (!p) return false;
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    return g_plans.count(p) != 0;
+}
+
+void plan_register(sp_plan p) {
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    g_plans.insert(p);
+}
+
+void plan_unregister(sp_plan p) {
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    g_plans.erase(p);
+}
+
+int validate_desc(const sp_desc* d) {
+    if (!d) return SP_ERR_INVALID_ARG;
+    if (d->n_lambda < 4 || (d->n_lambda & 1) || d->m_theta < 4) return SP_ERR_INVALID_ARG;
+    if (d->precision != SP_FP64 && d->precision != SP_MIXED) return SP_ERR_INVALID_ARG;
+    if (d->max_refine < 0 || (d->flags & ~SP_SYNC_INFO)) return SP_ERR_INVALID_ARG;
+    if (d->n_lambda > (1 << 20) || d->m_theta > (1 << 20)) return SP_ERR_UNSUPPORTED_SIZE;
+    std::vector<int> r;
+    if (!factorize(d->n_lambda / 2, r) || !factorize(d->m_theta, r)) return SP_ERR_UNSUPPORTED_SIZE;
+    return SP_OK;
+}
+
+struct Layout {
+    size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32;
+    size_t off_sin2, off_k0, off_fint, off_scal, total;
+    size_t spec_elems;
+};
+
+Layout layout_for(int n, int m, int rw) {
+    Layout L{};
+    size_t N = n / 2;
+    size_t nblk = (size_t)(m + rw - 1) / rw;
+    L.spec_elems = nblk * (N + 1) * rw;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
+    L.off_spec = take(L.spec_elems * sizeof(Cx<double>));
+    L.off_tw64n = take((size_t)n * sizeof(Cx<double>));
+    L.off_tw64m = take((size_t)m * sizeof(Cx<double>));
+    L.off_eq64 = take((size_t)m * sizeof(Cx<double>));
+    L.off_tw32n = take((size_t)n * sizeof(Cx<float>));
+    L.off_tw32m = take((size_t)m * sizeof(Cx<float>));
+    L.off_eq32 = take((size_t)m * sizeof(Cx<float>));
+    L.off_sin2 = take((size_t)m * sizeof(double));
+    L.off_k0 = take((size_t)2 * (m + 2) * sizeof(double));
+    L.off_fint = take((size_t)m * sizeof(double));
+    L.off_scal = take(16 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+// rows per lambda workgroup and threads per row
+bool lambda_schedule(int N, int m, const std::vector<int>& rad, size_t lds_limit, int* rw_log2,
+                     int* nthr, size_t* lds) {
+    int t = fft_threads(rad, N);
+    if (t > 1024) return false;
+    int best = -1;
+    for (int l = 0; l <= 5; ++l) {
+        int rw = 1 << l;
+        if (rw * t > 1024) break;
+        if ((size_t)rw * N * sizeof(Cx<double>) > lds_limit) break;
+        best = l;
+        if (rw >= m) break;
+        if (rw * t >= 256 && rw * (int)sizeof(Cx<double>) >= 128) break;
+    }
+    if (best < 0) return false;
+    *rw_log2 = best;
+    *nthr = t;
+    *lds = (size_t)(1 << best) * N * sizeof(Cx<double>);
+    return true;
+}
+
+template <typename T>
+size_t theta_lds_bytes(int m, int ptot) {
+    size_t a = (size_t)m * sizeof(Cx<T>);
+    size_t b = (size_t)ptot * (sizeof(Cx<T>) + 3 * sizeof(T));
+    size_t c = (size_t)ptot * (sizeof(Cx<double>) + sizeof(double));
+    return (std::max(a, std::max(b, c)) + 15) & ~(size_t)15;
+}
+
+int query_device(int* dev, size_t* lds_limit) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return SP_ERR_NO_DEVICE;
+    SP_HIP(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    SP_HIP(hipGetDeviceProperties(&prop, *dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_hip_err = std::string("device is ") + prop.gcnArchName + ", library is built for gfx950";
+        return SP_ERR_NO_DEVICE;
+    }
+    *lds_limit = prop.sharedMemPerBlock;
+    return SP_OK;
+}
+
+template <typename T>
+void set_lds_attr(const KernelSet<T>& ks, size_t lam, size_t theta) {
+    (void)hipFuncSetAttribute((const void*)ks.fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lam);
+    (void)hipFuncSetAttribute((const void*)ks.inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lam);
+    (void)hipFuncSetAttribute((const void*)ks.theta, hipFuncAttributeMaxDynamicSharedMemorySize, (int)theta);
+    (void)hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
+    if (validate_desc(d) != SP_OK) return 0;
+    std::vector<int> rl;
+    factorize(d->n_lambda / 2, rl);
+    int rwl = 0, nt = 0;
+    size_t lds = 0;
+    if (!lambda_schedule(d->n_lambda / 2, d->m_theta, rl, 160 * 1024, &rwl, &nt, &lds)) return 0;
+    return layout_for(d->n_lambda, d->m_theta, 1 << rwl).total;
+}
+
+extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_stream) {
+    if (!out) return SP_ERR_INVALID_ARG;
+    *out = nullptr;
+    int st = validate_desc(d);
+    if (st != SP_OK) return st;
+    int dev = 0;
+    size_t lds_limit = 0;
+    st = query_device(&dev, &lds_limit);
+    if (st != SP_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+
+    sp_plan p = new (std::nothrow) sp_plan_s();
+    if (!p) return SP_ERR_OOM;
+    p->desc = *d;
+    p->device = dev;
+    p->n = d->n_lambda;
+    p->m = d->m_theta;
+    p->N = p->n / 2;
+    const int n = p->n, m = p->m, N = p->N;
+
+    std::vector<int> rl, rt;
+    factorize(N, rl);
+    factorize(m, rt);
+    p->rmax = 1;
+    for (int r : rl) p->rmax = std::max(p->rmax, r);
+    for (int r : rt) p->rmax = std::max(p->rmax, r);
+    p->fft_lam = make_desc(rl, N, 2);
+    p->fft_theta = make_desc(rt, m, 1);
+
+    if (!lambda_schedule(N, m, rl, lds_limit, &p->rw_log2, &p->lam_threads, &p->lam_lds)) {
+        delete p;
+        return SP_ERR_UNSUPPORTED_SIZE;
+    }
+    p->theta_fft_threads = fft_threads(rt, m);
+    int ptotD = solve_threads(m, kSmaxD), ptotF = solve_threads(m, kSmaxF);
+    p->theta_threads = round_up(std::max(p->theta_fft_threads, std::max(ptotD, ptotF)), 64);
+    p->theta_lds64 = theta_lds_bytes<double>(m, ptotD);
+    p->theta_lds32 = theta_lds_bytes<float>(m, ptotF);
+    const size_t static_lds = 16 * sizeof(Cx<double>);
+    if (p->theta_threads > 1024 || p->theta_lds64 + static_lds > lds_limit) {
+        delete p;
+        return SP_ERR_UNSUPPORTED_SIZE;
+    }
+    p->k8 = (N + 1 + 7) / 8;
+    p->kd = pick_kernels<double>(p->rmax);
+    p->kf = pick_kernels<float>(p->rmax);
+    set_lds_attr(p->kd, p->lam_lds, p->theta_lds64);
+
+    // ---- device memory
+    Layout L = layout_for(n, m, 1 << p->rw_log2);
+    p->spec_elems = L.spec_elems;
+    hipError_t e = hipMalloc(&p->block, L.total);
+    if (e != hipSuccess) {
+        delete p;
+        (void)hipGetLastError();
+        return SP_ERR_OOM;
+    }
+    p->block_bytes = L.total;
+    unsigned char* b = (unsigned char*)p->block;
+    p->spec64 = (Cx<double>*)(b + L.off_spec);
+    p->t64.tw_n = (Cx<double>*)(b + L.off_tw64n);
+    p->t64.tw_m = (Cx<double>*)(b + L.off_tw64m);
+    p->t64.eq = (Cx<double>*)(b + L.off_eq64);
+    p->t32.tw_n = (Cx<float>*)(b + L.off_tw32n);
+    p->t32.tw_m = (Cx<float>*)(b + L.off_tw32m);
+    p->t32.eq = (Cx<float>*)(b + L.off_eq32);
+    p->sin2 = (double*)(b + L.off_sin2);
+    p->k0tab = (double*)(b + L.off_k0);
+    p->fint_w = (double*)(b + L.off_fint);
+    p->scal = (double*)(b + L.off_scal);
+
+    // ---- host tables
+    std::vector<Cx<double>> twn(n), twm(m), eq(m);
+    std::vector<Cx<float>> twn32(n), twm32(m), eq32(m);
+    for (int t = 0; t < n; ++t) cis_neg(t, n, &twn[t].x, &twn[t].y);
+    for (int t = 0; t < m; ++t) cis_neg(t, m, &twm[t].x, &twm[t].y);
+    for (int t = 0; t < m; ++t) cis_neg(t, 4LL * m, &eq[t].x, &eq[t].y);
+    for (int t = 0; t < n; ++t) twn32[t] = Cx<float>{(float)twn[t].x, (float)twn[t].y};
+    for (int t = 0; t < m; ++t) twm32[t] = Cx<float>{(float)twm[t].x, (float)twm[t].y};
+    for (int t = 0; t < m; ++t) eq32[t] = Cx<float>{(float)eq[t].x, (float)eq[t].y};
+    const long double PI = 3.141592653589793238462643383279502884L;
+    std::vector<double> sin2(m), fint(m);
+    for (int j = 0; j < m; ++j) {
+        long double th = ((long double)j + 0.5L) * PI / (long double)m;
+        long double s = sinl(th);
+        sin2[j] = (double)(s * s);
+        // Fejer-type weight: int_0^pi g sin = sum_j W_j g_j for g in span{cos q theta, q < m};
+        // the k = 0 column holds sin^2 f, so the integral of f uses W_j / sin^2(theta_j), times 2 pi.
+        long double W = 0.0L;
+        for (int q = 0; q < m; q += 2) {
+            long double cq = (q == 0 ? 1.0L : 2.0L) / (long double)m;
+            W += cq * cosl((long double)q * th) * 2.0L / (1.0L - (long double)q * q);
+        }
+        fint[j] = (double)(2.0L * PI * W / (s * s));
+    }
+    // k = 0 LU factors of the two cosine classes (even q >= 2, odd q), extended precision
+    std::vector<double> k0;
+    {
+        ClassCounts c = classes(m, false, true);
+        auto lu = [&](int q0, int nc) {
+            std::vector<long double> cp(nc);
+            std::vector<double> inv(nc), cpd(nc);
+            long double cprev = 0.0L;
+            for (int i = 0; i < nc; ++i) {
+                long double q = q0 + 2.0L * i;
+                long double sub = i == 0 ? 0.0L : (q - 2.0L) * (q - 1.0L) / 4.0L;
+                long double diag = -q * q / 2.0L;
+                long double sup = i == nc - 1 ? 0.0L : (q + 2.0L) * (q + 1.0L) / 4.0L;
+                long double den = diag - sub * cprev;
+                inv[i] = (double)(1.0L / den);
+                cp[i] = sup / den;
+                cpd[i] = (double)cp[i];
+                cprev = cp[i];
+            }
+            k0.insert(k0.end(), inv.begin(), inv.end());
+            k0.insert(k0.end(), cpd.begin(), cpd.end());
+        };
+        lu(2, c.ncA);
+        lu(1, c.ncB);
+    }
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    hipError_t ee = hipSuccess;
+    if (ee == hipSuccess) ee = up(p->t64.tw_n, twn.data(), n * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t64.tw_m, twm.data(), m * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t64.eq, eq.data(), m * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t32.tw_n, twn32.data(), n * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->t32.tw_m, twm32.data(), m * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->t32.eq, eq32.data(), m * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->sin2, sin2.data(), m * sizeof(double));
+    if (ee == hipSuccess) ee = up(p->k0tab, k0.data(), k0.size() * sizeof(double));
+    if (ee == hipSuccess) ee = up(p->fint_w, fint.data(), m * sizeof(double));
+    if (ee == hipSuccess) ee = hipStreamSynchronize(stream);
+    if (ee != hipSuccess) {
+        int r = hip_fail(ee, "uploading plan tables");
+        (void)hipFree(p->block);
+        delete p;
+        return r;
+    }
+    plan_register(p);
+    *out = p;
+    return SP_OK;
+}
+
+extern "C" int sphere_poisson_destroy(sp_plan p) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    plan_unregister(p);
+    int st = SP_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
+    if (p->block) {
+        e = hipFree(p->block);
+        if (e != hipSuccess && st == SP_OK) st = hip_fail(e, "hipFree");
+    }
+    delete p;
+    return st;
+}
+
+namespace {
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+// One FP64 pass over the three kernels: lambda forward, theta, lambda inverse.
+int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool fwd_sin2,
+             bool adjoint_weights, bool want_fint, hipStream_t s) {
+    const int n = p->n, m = p->m, N = p->N;
+    const int rw = 1 << p->rw_log2;
+    const int nblk = (m + rw - 1) / rw;
+    sp::LambdaArgs<double> la{};
+    la.x = in;
+    la.y = out;
+    la.spec = p->spec64;
+    la.tw = p->t64.tw_n;
+    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2;
+    la.fft = p->fft_lam;
+    la.nthr = p->lam_threads;
+    // forward lambda
+    la.rowscale = fwd_sin2 ? p->sin2 : nullptr;
+    if (!adjoint_weights) { la.w_mid = 1.0 / n; la.w_end = 1.0 / n; }
+    else { la.w_mid = 2.0; la.w_end = 1.0; }
+    hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    // theta
+    sp::ThetaArgs<double> ta{};
+    ta.spec = p->spec64;
+    ta.tw = p->t64.tw_m;
+    ta.eq = p->t64.eq;
+    ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2;
+    ta.fft = p->fft_theta;
+    ta.nthr_fft = p->theta_fft_threads;
+    ta.mode = mode;
+    ta.k8 = p->k8;
+    ta.c0 = c0;
+    ta.k0tab = p->k0tab;
+    ta.fint_w = want_fint ? p->fint_w : nullptr;
+    ta.fint_out = p->scal;
+    hipLaunchKernelGGL(p->kd.theta, dim3(8 * p->k8), dim3(p->theta_threads), p->theta_lds64, s, ta);
+    // inverse lambda
+    if (!adjoint_weights) { la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0; la.rowscale = nullptr; }
+    else { la.w_mid = 0.5; la.w_end = 1.0; la.out_scale = 1.0 / n; la.rowscale = p->sin2; }
+    hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
+}
+
+int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status) {
+    if (!(p->desc.flags & SP_SYNC_INFO)) return status;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    double fint = 0.0;
+    e = hipMemcpy(&fint, p->scal, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy info");
+    if (info) {
+        info->iters = 0;
+        info->rel_correction = 0.0;
+        info->f_integral = fint;
+        info->status = status;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" int sphere_poisson_solve(sp_plan p, const double* f, double* u, double integral,
+                                    void* hip_stream, sp_info* info) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!f || !u) return SP_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
+    if (overlap(f, u, bytes)) return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double PI = 3.14159265358979323846;
+    int st = run_fp64(p, f, u, sp::kSolve, integral / (4.0 * PI), true, false, true, s);
+    if (st != SP_OK) return st;
+    return finish_info(p, s, info, SP_OK);
+}
+
+extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* fbar, void* hip_stream,
+                                            sp_info* info) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!g || !fbar) return SP_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
+    if (overlap(g, fbar, bytes)) return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int st = run_fp64(p, g, fbar, sp::kSolveTransposed, 0.0, false, true, false, s);
+    if (st != SP_OK) return st;
+    return finish_info(p, s, info, SP_OK);
+}
+
+extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, double* out, void* hip_stream) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!f || !out) return SP_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
+    if (overlap(f, out, bytes)) return SP_ERR_ALIAS;
+    return run_fp64(p, f, out, sp::kTransformOnly, 0.0, true, false, false, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_solve_batch(int count, const int* n, const int* m, const double* const* f,
+                                          double* const* u, int precision, void* hip_stream, sp_info* infos) {
+    (void)precision; (void)hip_stream; (void)infos;
+    if (count <= 0 || !n || !m || !f || !u) return SP_ERR_INVALID_ARG;
+    return SP_ERR_UNSUPPORTED_SIZE;
+}
+
+extern "C" const char* sphere_poisson_strerror(int code) {
+    switch (code) {
+        case SP_OK: return "success";
+        case SP_ERR_INVALID_ARG: return "invalid argument";
+        case SP_ERR_UNSUPPORTED_SIZE: return "unsupported size (prime factor > 31 or too large)";
+        case SP_ERR_OOM: return "device out of memory";
+        case SP_ERR_HIP: {
+            static thread_local std::string msg;
+            msg = "HIP error: " + g_hip_err;
+            return msg.c_str();
+        }
+        case SP_ERR_NOT_CONVERGED: return "refinement did not reach the requested tolerance";
+        case SP_ERR_ALIAS: return "input and output buffers overlap";
+        case SP_ERR_NO_DEVICE: {
+            static thread_local std::string msg;
+            msg = "no usable gfx950 device" + (g_hip_err.empty() ? std::string() : ": " + g_hip_err);
+            return msg.c_str();
+        }
+        case SP_ERR_BAD_PLAN: return "null or destroyed plan";
+        default: return "unknown status";
+    }
+}
