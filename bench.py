@@ -1,0 +1,160 @@
+"""Benchmark of the DFS spectral Poisson solver on one MI355X.
+
+Workload (one step = one complete solve, every stage of the hot path):
+n = m = 10000 grid (1e8 degrees of freedom), f a seeded band-limited random
+spherical-harmonic field with degree l <= 2000 and c_lM ~ N(0,1)/(1+l)^2,
+float64 samples in and out, inputs resident in HBM before timing.
+
+Prints ONE JSON line: DOF/s (whole job), the HIP-event roofline of the
+dominant kernel, the CPU oracle baseline on the same workload, and the
+accuracy of the timed result against the closed-form solution and the FP64
+oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "sphere Poisson DOF/s at 1e-10 rel err (FP32+refine vs FP64); HBM GB/s"
+
+WORKLOADS = {
+    # name: (n, m, L, cfg seed)
+    "sphere_poisson_n10000_m10000_l2000": (10000, 10000, 2000, 2),
+    "sphere_poisson_n1024_m1024_l256": (1024, 1024, 256, 1),
+}
+
+
+def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
+    """Algorithmic HBM bytes of one launch (what the kernel must read and write)."""
+    N = n // 2
+    spec64 = m * (N + 1) * 16
+    spec32 = m * (N + 1) * 8
+    grid = m * n * 8
+    table = {
+        "lambda_fwd": grid + spec64,
+        "theta": 2 * spec64 if precision == "fp64" else spec64 + spec32,
+        "lambda_inv": spec64 + grid,
+        "lambda_mix": spec32 + spec64,
+        "theta_resid": 2 * spec64 + spec32,
+        "lambda_upd": 2 * spec32 + grid,
+    }
+    return table[kind]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="fp64")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sphere_poisson_n10000_m10000_l2000")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1510_08094_amd as P
+    import sh_inputs as S
+
+    n, m, L, cfg = WORKLOADS[args.workload]
+    dof = n * m
+    log("bench: synthesising f (n=%d m=%d l<=%d)" % (n, m, L))
+    t0 = time.time()
+    if args.no_check:
+        f, u_exact = S.sphere_field(cfg, 0, n, m, L), None
+    else:
+        f, u_exact = S.sphere_field(cfg, 0, n, m, L, with_solution=True)
+    log("bench: inputs ready in %.1fs" % (time.time() - t0))
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    fg = torch.from_numpy(f).to(dev)
+    ug = torch.empty_like(fg)
+    plan = P.SpherePoisson(n, m, args.precision)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        plan.solve(fg, out=ug)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    plan.profile_enable(16 * args.steps)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        plan.solve(fg, out=ug)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    prof = plan.profile_read()
+    plan.profile_enable(0)
+    ms_per_step = total_ms / args.steps
+    value = dof / (ms_per_step * 1e-3)
+    log("bench: %.3f ms/step, %.3e DOF/s, kernels %s" % (ms_per_step, value, prof))
+
+    kernels = {}
+    for kind, (tot, cnt) in prof.items():
+        avg_ms = tot / cnt
+        b = kernel_bytes(kind, n, m, args.precision)
+        kernels[kind] = {"avg_ms": round(avg_ms, 5), "launches": cnt, "alg_bytes": b,
+                         "alg_GBps": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    achieved = kernels[dom]["alg_GBps"]
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (seeded band-limited spherical-harmonic field)",
+        "config": {"workload": args.workload, "n_lambda": n, "m_theta": m, "dof": dof, "l_max": L,
+                   "precision": args.precision, "rhs": 1},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "kernels": kernels,
+        "paper_context_dof_per_s": 1e8 / 60.0,
+    }
+
+    if not args.no_check:
+        torch.cuda.synchronize()
+        u = ug.cpu().numpy()
+        out["rel_err_vs_closed_form"] = float(np.linalg.norm(u - u_exact) / np.linalg.norm(u_exact))
+        del u_exact
+    else:
+        u = None
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("bench: timing the CPU oracle on the full workload")
+        t0 = time.perf_counter()
+        u_or = O.solve_reduced(f)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+                               "sample": "one full %dx%d solve (reduced-mode float64 oracle, numpy/scipy "
+                                         "single-threaded), %.1f s" % (n, m, dt),
+                               "host_cpus": os.cpu_count()}
+        if u is not None:
+            out["rel_err_vs_oracle"] = float(np.linalg.norm(u - u_or) / np.linalg.norm(u_or))
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

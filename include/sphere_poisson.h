@@ -142,6 +142,29 @@ size_t sphere_poisson_workspace_bytes(const sp_desc* desc);
 int sphere_poisson_transform_roundtrip(sp_plan plan, const double* f, double* out,
                                        void* hip_stream);
 
+/* Kernel kinds reported by the profiling calls below. */
+typedef enum {
+    SP_KERNEL_LAMBDA_FWD = 0,   /* lambda real DFT of a block of rows (writes the half spectrum) */
+    SP_KERNEL_THETA = 1,        /* per-wavenumber theta transform + banded solve + inverse */
+    SP_KERNEL_LAMBDA_INV = 2,   /* inverse lambda real DFT of a block of rows */
+    SP_KERNEL_LAMBDA_MIX = 3,   /* MIXED: float32 inverse + float64 forward lambda DFT of the first iterate */
+    SP_KERNEL_THETA_RESID = 4,  /* MIXED: float64 residual in coefficient space + float32 correction solve */
+    SP_KERNEL_LAMBDA_UPD = 5,   /* MIXED: float32 inverse lambda DFTs + float64 update of u */
+    SP_KERNEL_REDUCE = 6,       /* norms for the convergence report */
+    SP_KERNEL_KINDS = 7
+} sp_kernel_kind;
+
+/* Diagnostic profiling: with `capacity` > 0 every later kernel launch of this
+ * plan is bracketed by HIP events recorded on the launch stream, until
+ * `capacity` launches have been recorded (0 disables and frees the events).
+ * Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG (capacity < 0), SP_ERR_HIP. */
+int sphere_poisson_profile_enable(sp_plan plan, int capacity);
+
+/* Waits for the recorded launches and returns, per sp_kernel_kind, the summed
+ * duration in milliseconds (total_ms[SP_KERNEL_KINDS]) and the launch count
+ * (counts[SP_KERNEL_KINDS]); then clears the record.  Either array may be NULL. */
+int sphere_poisson_profile_read(sp_plan plan, double* total_ms, int* counts);
+
 #ifdef __cplusplus
 }
 #endif

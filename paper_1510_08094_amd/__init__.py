@@ -81,7 +81,9 @@ def library():
     lib.sphere_poisson_workspace_bytes.argtypes = [ctypes.POINTER(SpDesc)]
     lib.sphere_poisson_workspace_bytes.restype = ctypes.c_size_t
     lib.sphere_poisson_transform_roundtrip.argtypes = [vp, vp, vp, vp]
-    for name in ("sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
+    lib.sphere_poisson_profile_enable.argtypes = [vp, ci]
+    lib.sphere_poisson_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
+    for name in ("sphere_poisson_profile_enable", "sphere_poisson_profile_read", "sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
                  "sphere_poisson_transform_roundtrip"):
         getattr(lib, name).restype = ci
@@ -157,6 +159,20 @@ class SpherePoisson:
                 self._plan, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                 ctypes.c_void_p(_stream_handle(self.device))))
         return out
+
+    KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce")
+
+    def profile_enable(self, capacity: int):
+        """Bracket the next `capacity` kernel launches with HIP events."""
+        _check(library().sphere_poisson_profile_enable(self._plan, int(capacity)))
+
+    def profile_read(self) -> dict:
+        """{kind: (total_ms, launches)} of the recorded launches (then cleared)."""
+        n = len(self.KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(library().sphere_poisson_profile_read(self._plan, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_KINDS) if cnt[i]}
 
     def close(self):
         if self._plan:

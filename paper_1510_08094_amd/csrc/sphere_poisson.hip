@@ -179,6 +179,10 @@ struct sp_plan_s {
     double* fint_w = nullptr;
     double* scal = nullptr;   // device scalars: [0] = integral of f
     size_t spec_elems = 0;
+    // profiling: event pairs around launches
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
 };
 
 namespace {
@@ -310,6 +314,10 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     *out = nullptr;
     int st = validate_desc(d);
     if (st != SP_OK) return st;
+    if (d->precision != SP_FP64) {
+        g_hip_err = "the mixed-precision path is not built yet";
+        return SP_ERR_INVALID_ARG;
+    }
     int dev = 0;
     size_t lds_limit = 0;
     st = query_device(&dev, &lds_limit);
@@ -450,12 +458,59 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     return SP_OK;
 }
 
+namespace {
+void free_events(sp_plan p) {
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
+    p->ev_kind.clear();
+    p->ev_used = 0;
+}
+}  // namespace
+
+extern "C" int sphere_poisson_profile_enable(sp_plan p, int capacity) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (capacity < 0) return SP_ERR_INVALID_ARG;
+    SP_HIP(hipDeviceSynchronize());
+    free_events(p);
+    p->ev.resize(2 * (size_t)capacity);
+    for (size_t i = 0; i < p->ev.size(); ++i) {
+        hipError_t e = hipEventCreate(&p->ev[i]);
+        if (e != hipSuccess) {
+            p->ev.resize(i);
+            free_events(p);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    p->ev_kind.assign(capacity, -1);
+    return SP_OK;
+}
+
+extern "C" int sphere_poisson_profile_read(sp_plan p, double* total_ms, int* counts) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    double tot[SP_KERNEL_KINDS] = {0};
+    int cnt[SP_KERNEL_KINDS] = {0};
+    for (int i = 0; i < p->ev_used; ++i) {
+        SP_HIP(hipEventSynchronize(p->ev[2 * i + 1]));
+        float ms = 0.f;
+        SP_HIP(hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]));
+        int k = p->ev_kind[i];
+        if (k >= 0 && k < SP_KERNEL_KINDS) { tot[k] += ms; cnt[k] += 1; }
+    }
+    p->ev_used = 0;
+    for (int k = 0; k < SP_KERNEL_KINDS; ++k) {
+        if (total_ms) total_ms[k] = tot[k];
+        if (counts) counts[k] = cnt[k];
+    }
+    return SP_OK;
+}
+
 extern "C" int sphere_poisson_destroy(sp_plan p) {
     if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
     plan_unregister(p);
     int st = SP_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
+    free_events(p);
     if (p->block) {
         e = hipFree(p->block);
         if (e != hipSuccess && st == SP_OK) st = hip_fail(e, "hipFree");
@@ -465,6 +520,23 @@ extern "C" int sphere_poisson_destroy(sp_plan p) {
 }
 
 namespace {
+
+// Launch bracketing for the profiling calls (no-ops unless enabled).
+struct ProfScope {
+    sp_plan p;
+    hipStream_t s;
+    int slot = -1;
+    ProfScope(sp_plan p_, int kind, hipStream_t s_) : p(p_), s(s_) {
+        if (p->ev_used < (int)p->ev_kind.size()) {
+            slot = p->ev_used++;
+            p->ev_kind[slot] = kind;
+            (void)hipEventRecord(p->ev[2 * slot], s);
+        }
+    }
+    ~ProfScope() {
+        if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], s);
+    }
+};
 
 bool overlap(const void* a, const void* b, size_t bytes) {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
@@ -489,7 +561,10 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     la.rowscale = fwd_sin2 ? p->sin2 : nullptr;
     if (!adjoint_weights) { la.w_mid = 1.0 / n; la.w_end = 1.0 / n; }
     else { la.w_mid = 2.0; la.w_end = 1.0; }
-    hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    }
     // theta
     sp::ThetaArgs<double> ta{};
     ta.spec = p->spec64;
@@ -504,11 +579,17 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     ta.k0tab = p->k0tab;
     ta.fint_w = want_fint ? p->fint_w : nullptr;
     ta.fint_out = p->scal;
-    hipLaunchKernelGGL(p->kd.theta, dim3(8 * p->k8), dim3(p->theta_threads), p->theta_lds64, s, ta);
+    {
+        ProfScope ps(p, SP_KERNEL_THETA, s);
+        hipLaunchKernelGGL(p->kd.theta, dim3(8 * p->k8), dim3(p->theta_threads), p->theta_lds64, s, ta);
+    }
     // inverse lambda
     if (!adjoint_weights) { la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0; la.rowscale = nullptr; }
     else { la.w_mid = 0.5; la.w_end = 1.0; la.out_scale = 1.0 / n; la.rowscale = p->sin2; }
-    hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
+        hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return SP_OK;

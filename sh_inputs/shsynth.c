@@ -23,22 +23,21 @@
  *   Pbar_{M+1}^M = sqrt(2M+3) cos(theta) Pbar_M^M
  *   Pbar_l^M = a_lM (cos(theta) Pbar_{l-1}^M - b_lM Pbar_{l-2}^M),
  *     a_lM = sqrt((4l^2-1)/(l^2-M^2)), b_lM = sqrt(((l-1)^2-M^2)/(4(l-1)^2-1)).
- * Values that would underflow are flushed to zero (they are below 1e-300 and
- * cannot affect a double-precision field).
+ * Sectoral values (sin theta)^M fall far below the double range near the
+ * poles for large M, while the recurrence in l later grows them back by up to
+ * hundreds of orders of magnitude.  They are therefore carried as
+ * value * 2^e with an integer exponent e (a multiple of 400, e <= 0).  The
+ * recurrence runs on the scaled value; whenever the true value reaches 2^-600
+ * it is converted back to an ordinary double (e = 0), and while it is smaller
+ * a scaled value above 2^400 is renormalised by 2^-400.  Terms whose true value
+ * stays below 2^-600 (about 1e-181) are left out of the sums.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
-#include <xmmintrin.h>
-#include <pmmintrin.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
-
-static void set_ftz(void) {
-    _MM_SET_FLUSH_ZERO_MODE(_MM_FLUSH_ZERO_ON);
-    _MM_SET_DENORMALS_ZERO_MODE(_MM_DENORMALS_ZERO_ON);
-}
 
 /* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
  * A and B are [nsets][L+1][m] row-major (theta fastest). */
@@ -47,41 +46,43 @@ int sh_legendre_sums(int m, int L, int nsets, const double* coeffs,
     if (m < 1 || L < 0 || nsets < 1 || !coeffs || !A || !B) return -1;
     const int half = (m + 1) / 2;          /* theta_j for j < half lie in (0, pi/2] */
     const long ncoef = (long)(L + 1) * (L + 1) - 1;
+    const double up = 0x1p400, down = 0x1p-400;
     double* x = (double*)malloc(sizeof(double) * half);
     double* s = (double*)malloc(sizeof(double) * half);
     double* pmm = (double*)malloc(sizeof(double) * (size_t)(L + 1) * half);
-    if (!x || !s || !pmm) { free(x); free(s); free(pmm); return -2; }
+    int* pme = (int*)malloc(sizeof(int) * (size_t)(L + 1) * half);
+    if (!x || !s || !pmm || !pme) { free(x); free(s); free(pmm); free(pme); return -2; }
     for (int j = 0; j < half; ++j) {
         double th = (j + 0.5) * M_PI / m;
         x[j] = cos(th);
         s[j] = sin(th);
     }
-    /* Sectoral values Pbar_M^M(theta_j), running product in M. */
-    {
-        unsigned int csr = _mm_getcsr();
-        set_ftz();
-        for (int j = 0; j < half; ++j) pmm[j] = 1.0 / sqrt(4.0 * M_PI);
-        for (int M = 1; M <= L; ++M) {
-            double f = sqrt((2.0 * M + 1.0) / (2.0 * M));
-            double* cur = pmm + (size_t)M * half;
-            const double* prv = pmm + (size_t)(M - 1) * half;
-            for (int j = 0; j < half; ++j) cur[j] = f * s[j] * prv[j];
+    /* Sectoral values Pbar_M^M(theta_j) = pmm * 2^pme: running product in M */
+    for (int j = 0; j < half; ++j) { pmm[j] = 1.0 / sqrt(4.0 * M_PI); pme[j] = 0; }
+    for (int M = 1; M <= L; ++M) {
+        double f = sqrt((2.0 * M + 1.0) / (2.0 * M));
+        double* cur = pmm + (size_t)M * half;
+        const double* prv = pmm + (size_t)(M - 1) * half;
+        int* ce = pme + (size_t)M * half;
+        const int* pe = pme + (size_t)(M - 1) * half;
+        for (int j = 0; j < half; ++j) {
+            double v = f * s[j] * prv[j];
+            int e = pe[j];
+            if (v < down) { v *= up; e -= 400; }
+            cur[j] = v;
+            ce[j] = e;
         }
-        _mm_setcsr(csr);
     }
     memset(A, 0, sizeof(double) * (size_t)nsets * (L + 1) * m);
     memset(B, 0, sizeof(double) * (size_t)nsets * (L + 1) * m);
     int failed = 0;
 #pragma omp parallel
     {
-        unsigned int csr = _mm_getcsr();
-        set_ftz();
-        /* per-thread work arrays: previous two Legendre rows and the
-         * even/odd (in l+M) accumulators for every set and both signs of M */
         double* p0 = (double*)malloc(sizeof(double) * half);
         double* p1 = (double*)malloc(sizeof(double) * half);
+        int* ex = (int*)malloc(sizeof(int) * half);
         double* acc = (double*)malloc(sizeof(double) * (size_t)4 * nsets * half);
-        if (!p0 || !p1 || !acc) {
+        if (!p0 || !p1 || !ex || !acc) {
 #pragma omp atomic write
             failed = 1;
         } else {
@@ -89,22 +90,48 @@ int sh_legendre_sums(int m, int L, int nsets, const double* coeffs,
             for (int M = 0; M <= L; ++M) {
                 memset(acc, 0, sizeof(double) * (size_t)4 * nsets * half);
                 const double* pm = pmm + (size_t)M * half;
-                for (int j = 0; j < half; ++j) { p0[j] = 0.0; p1[j] = pm[j]; }
-                /* p1 holds Pbar_l^M for the current l, p0 the previous l */
+                const int* pe = pme + (size_t)M * half;
+                /* the scaled entries form a prefix j < jz (sin theta grows with j) */
+                int jz = 0;
+                for (int j = 0; j < half; ++j) {
+                    p0[j] = 0.0;
+                    p1[j] = pm[j];
+                    ex[j] = pe[j];
+                    if (ex[j] < 0 && fabs(p1[j]) >= ldexp(1.0, -600 - ex[j])) {
+                        p1[j] = ldexp(p1[j], ex[j]);
+                        ex[j] = 0;
+                    }
+                    if (ex[j] < 0) jz = j + 1;
+                }
+                /* p1 holds Pbar_l^M (times 2^-ex) for the current l, p0 the previous l */
                 for (int l = M; l <= L; ++l) {
+                    double a = 0.0, b = 0.0;
                     if (l == M + 1) {
-                        double a = sqrt(2.0 * M + 3.0);
-                        for (int j = 0; j < half; ++j) {
-                            double nv = a * x[j] * p1[j];
-                            p0[j] = p1[j];
-                            p1[j] = nv;
-                        }
+                        a = sqrt(2.0 * M + 3.0);
                     } else if (l > M + 1) {
                         double ll = (double)l, mm = (double)M;
-                        double a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
-                        double b = sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) /
-                                        (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
-                        for (int j = 0; j < half; ++j) {
+                        a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+                        b = sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+                    }
+                    if (l > M) {
+                        for (int j = 0; j < jz; ++j) {
+                            double nv = a * (x[j] * p1[j] - b * p0[j]);
+                            p0[j] = p1[j];
+                            p1[j] = nv;
+                            if (ex[j] < 0) {
+                                if (fabs(nv) > up) {
+                                    p0[j] *= down;
+                                    p1[j] *= down;
+                                    ex[j] += 400;
+                                }
+                                if (ex[j] < 0 && fabs(p1[j]) >= ldexp(1.0, -600 - ex[j])) {
+                                    p0[j] = ldexp(p0[j], ex[j]);
+                                    p1[j] = ldexp(p1[j], ex[j]);
+                                    ex[j] = 0;
+                                }
+                            }
+                        }
+                        for (int j = jz; j < half; ++j) {
                             double nv = a * (x[j] * p1[j] - b * p0[j]);
                             p0[j] = p1[j];
                             p1[j] = nv;
@@ -118,7 +145,13 @@ int sh_legendre_sums(int m, int L, int nsets, const double* coeffs,
                         double cn = (M > 0) ? c[(long)l * l - 1 + (-M + l)] : 0.0;
                         double* ap = acc + ((size_t)(4 * t + 2 * 0 + odd)) * half;
                         double* an = acc + ((size_t)(4 * t + 2 * 1 + odd)) * half;
-                        for (int j = 0; j < half; ++j) {
+                        for (int j = 0; j < jz; ++j) {
+                            if (ex[j] == 0) {
+                                ap[j] += cp * p1[j];
+                                an[j] += cn * p1[j];
+                            }
+                        }
+                        for (int j = jz; j < half; ++j) {
                             ap[j] += cp * p1[j];
                             an[j] += cn * p1[j];
                         }
@@ -144,9 +177,8 @@ int sh_legendre_sums(int m, int L, int nsets, const double* coeffs,
                 }
             }
         }
-        free(p0); free(p1); free(acc);
-        _mm_setcsr(csr);
+        free(p0); free(p1); free(ex); free(acc);
     }
-    free(x); free(s); free(pmm);
+    free(x); free(s); free(pmm); free(pme);
     return failed ? -2 : 0;
 }

@@ -367,3 +367,11 @@ def test_planted_wrong_constraint_is_caught(monkeypatch):
         return out
     monkeypatch.setattr(O.sphere_poisson, "_solve_columns", bad)
     assert _closed_form_error(O.solve_reduced) > 1e-8
+
+
+def test_closed_form_degree_2000():
+    """l <= 2000 reaches orders M whose sectoral values (sin theta)^M underflow
+    double precision near the poles; the generator must still produce exact
+    band-limited fields (regression: dropping them broke the closed form)."""
+    f, u = S.sphere_field(2, 0, 4096, 2100, 2000, with_solution=True)
+    assert rel2(O.solve_reduced(f, 0.0), u) <= 1e-13
