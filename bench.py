@@ -40,7 +40,8 @@ def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
     grid = m * n * 8
     table = {
         "lambda_fwd": grid + spec64,
-        "theta": 2 * spec64 if precision == "fp64" else spec64 + spec32,
+        # mixed first solve: reads sin^2 b, writes F in place and the float32 solution spectrum
+        "theta": 2 * spec64 if precision == "fp64" else 2 * spec64 + spec32,
         "lambda_inv": spec64 + grid,
         "lambda_mix": spec32 + spec64,
         "theta_resid": 2 * spec64 + spec32,
@@ -58,10 +59,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="fp64")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sphere_poisson_n10000_m10000_l2000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -110,6 +112,26 @@ def main():
     value = dof / (ms_per_step * 1e-3)
     log("bench: %.3f ms/step, %.3e DOF/s, kernels %s" % (ms_per_step, value, prof))
 
+    fp64_ref = None
+    if args.precision == "mixed" and not args.no_fp64_ref:
+        # the plain float64 solver on the same input, same protocol (context for the mixed speed-up)
+        p64 = P.SpherePoisson(n, m, "fp64")
+        u64 = torch.empty_like(fg)
+        for _ in range(args.warmup):
+            p64.solve(fg, out=u64)
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            p64.solve(fg, out=u64)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = s0.elapsed_time(s1) / args.steps
+        fp64_ref = {"ms_per_step": ms64, "dof_per_s": dof / (ms64 * 1e-3)}
+        p64.close()
+        del u64
+        log("bench: float64 solver %.3f ms/step" % ms64)
+
     kernels = {}
     for kind, (tot, cnt) in prof.items():
         avg_ms = tot / cnt
@@ -131,6 +153,9 @@ def main():
         "kernels": kernels,
         "paper_context_dof_per_s": 1e8 / 60.0,
     }
+    if fp64_ref is not None:
+        out["fp64_solver"] = fp64_ref
+        out["speedup_vs_fp64_solver"] = value / fp64_ref["dof_per_s"]
 
     if not args.no_check:
         torch.cuda.synchronize()

@@ -77,6 +77,9 @@ typedef struct {
     int max_refine;     /* MIXED: number of iterative-refinement corrections (>= 0; 1 is enough for 1e-10) */
     double tol;         /* MIXED with SP_SYNC_INFO: required ||last correction|| / ||u|| (<= 0: no check) */
     unsigned flags;     /* SP_SYNC_INFO */
+    int low_k_fp64;     /* MIXED: wavenumbers k < low_k_fp64 are eliminated in float64 (their systems
+                           have condition numbers near (m/k)^2, too large for float32 corrections);
+                           < 0: automatic, max(16, m/64); 0 or 1: only k = 0 */
 } sp_desc;
 
 typedef struct {

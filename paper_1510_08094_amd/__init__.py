@@ -41,7 +41,8 @@ class SpError(RuntimeError):
 
 class SpDesc(ctypes.Structure):
     _fields_ = [("n_lambda", ctypes.c_int), ("m_theta", ctypes.c_int), ("precision", ctypes.c_int),
-                ("max_refine", ctypes.c_int), ("tol", ctypes.c_double), ("flags", ctypes.c_uint)]
+                ("max_refine", ctypes.c_int), ("tol", ctypes.c_double), ("flags", ctypes.c_uint),
+                ("low_k_fp64", ctypes.c_int)]
 
 
 class SpInfo(ctypes.Structure):
@@ -115,14 +116,14 @@ class SpherePoisson:
     """A plan for one grid size and precision (owns the device workspace)."""
 
     def __init__(self, n: int, m: int, precision: str = "fp64", max_refine: int = 1, tol: float = 0.0,
-                 sync_info: bool = False, device=None):
+                 sync_info: bool = False, device=None, low_k_fp64: int = -1):
         lib = library()
         self.n, self.m = int(n), int(m)
         self.precision = {"fp64": SP_FP64, "mixed": SP_MIXED}[precision]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.desc = SpDesc(self.n, self.m, self.precision, int(max_refine), float(tol),
-                           SP_SYNC_INFO if sync_info else 0)
+                           SP_SYNC_INFO if sync_info else 0, int(low_k_fp64))
         self._plan = ctypes.c_void_p()
         self.info = SpInfo()
         with torch.cuda.device(self.device):

@@ -35,17 +35,86 @@ struct LambdaArgs {
     int nthr;               // threads per row
 };
 
+// Block layout helpers: a lambda workgroup owns rows jb*RW .. jb*RW+RW-1; row r
+// of the block uses LDS line `lines + r * stride`.
+__device__ __forceinline__ size_t spec_index(int jb, int k, int jj, int N, int rwl) {
+    return (((size_t)jb * (N + 1) + k) << rwl) + jj;
+}
+
+// Split the length-N complex DFT of every row into the half spectrum X_0..X_N
+// (times w_mid for 0<k<N, w_end for k in {0, N}) and store it (type TS).
+// Lanes run over (pair, row) with the row fastest, so stores are contiguous.
+template <typename T, typename TS>
+__device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t stride, Cx<TS>* spec,
+                                                const Cx<T>* tw, int N, int rwl, int m, int jb,
+                                                T w_mid, T w_end) {
+    const int rw = 1 << rwl;
+    const int npairs = N / 2 + 1;
+    for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
+        const int jj = e & (rw - 1);
+        const int k = e >> rwl;
+        if ((jb << rwl) + jj >= m) continue;
+        const Cx<T>* b = lines + (size_t)jj * stride;
+        if (k == 0) {
+            const Cx<T> z = b[0];
+            spec[spec_index(jb, 0, jj, N, rwl)] = Cx<TS>{(TS)((z.x + z.y) * w_end), (TS)0};
+            spec[spec_index(jb, N, jj, N, rwl)] = Cx<TS>{(TS)((z.x - z.y) * w_end), (TS)0};
+            continue;
+        }
+        const Cx<T> zk = b[k], zn = b[N - k];
+        const Cx<T> E = (zk + cconj(zn)) * (T)0.5;
+        const Cx<T> O = mul_negi(zk - cconj(zn)) * (T)0.5;
+        const Cx<T> WO = cmul(tw[k], O);
+        const Cx<T> xk = (E + WO) * w_mid;
+        spec[spec_index(jb, k, jj, N, rwl)] = Cx<TS>{(TS)xk.x, (TS)xk.y};
+        if (N - k != k) {
+            const Cx<T> xn = cconj(E - WO) * w_mid;
+            spec[spec_index(jb, N - k, jj, N, rwl)] = Cx<TS>{(TS)xn.x, (TS)xn.y};
+        }
+    }
+}
+
+// Read the half spectrum of every row (type TS, times w_mid / w_end) and build
+// the length-N complex sequence whose inverse DFT interleaves the real output.
+template <typename T, typename TS>
+__device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, const Cx<TS>* spec,
+                                                 const Cx<T>* tw, int N, int rwl, int m, int jb,
+                                                 T w_mid, T w_end) {
+    const int rw = 1 << rwl;
+    const int npairs = N / 2 + 1;
+    for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
+        const int jj = e & (rw - 1);
+        const int k = e >> rwl;
+        if ((jb << rwl) + jj >= m) continue;
+        Cx<T>* b = lines + (size_t)jj * stride;
+        if (k == 0) {
+            const T x0 = (T)spec[spec_index(jb, 0, jj, N, rwl)].x * w_end;
+            const T xN = (T)spec[spec_index(jb, N, jj, N, rwl)].x * w_end;
+            b[0] = Cx<T>{x0 + xN, x0 - xN};
+            continue;
+        }
+        const Cx<TS> sk = spec[spec_index(jb, k, jj, N, rwl)];
+        const Cx<TS> sn = spec[spec_index(jb, N - k, jj, N, rwl)];
+        const Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
+        const Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
+        const Cx<T> P = xk + cconj(xn);
+        const Cx<T> Q = xk - cconj(xn);
+        const Cx<T> iWQ = mul_i(cmulc(Q, tw[k]));   // i conj(W) Q
+        b[k] = P + iWQ;
+        if (N - k != k) b[N - k] = cconj(P - iWQ);
+    }
+}
+
 template <typename T, int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<T>* lines = reinterpret_cast<Cx<T>*>(smem_raw);
-    const int rw = 1 << a.rw_log2;
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
     const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
-    const bool active = line < rw && j < a.m;
+    const bool active = line < (1 << a.rw_log2) && j < a.m;
     Cx<T>* buf = lines + (size_t)line * N;
     if (active) {
         const double s = a.rowscale ? a.rowscale[j] : 1.0;
@@ -57,61 +126,20 @@ __global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
     }
     __syncthreads();
     fft_lds<T, false, EPT, RMAX>(buf, a.fft, a.tw, t, a.nthr, active);
-    // split into the real-input spectrum; lanes run over (pair, row) with the row fastest
-    const int npairs = N / 2 + 1;
-    const size_t blk = (size_t)jb * (N + 1);
-    for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
-        const int jj = e & (rw - 1);
-        const int k = e >> a.rw_log2;
-        if ((jb << a.rw_log2) + jj >= a.m) continue;
-        const Cx<T>* b = lines + (size_t)jj * N;
-        if (k == 0) {
-            const Cx<T> z = b[0];
-            a.spec[(blk + 0) * rw + jj] = Cx<T>{(z.x + z.y) * a.w_end, (T)0};
-            a.spec[(blk + N) * rw + jj] = Cx<T>{(z.x - z.y) * a.w_end, (T)0};
-            continue;
-        }
-        const Cx<T> zk = b[k], zn = b[N - k];
-        const Cx<T> E = (zk + cconj(zn)) * (T)0.5;
-        const Cx<T> O = mul_negi(zk - cconj(zn)) * (T)0.5;
-        const Cx<T> WO = cmul(a.tw[k], O);
-        a.spec[(blk + k) * rw + jj] = (E + WO) * a.w_mid;
-        if (N - k != k) a.spec[(blk + N - k) * rw + jj] = cconj(E - WO) * a.w_mid;
-    }
+    r2c_split_store<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
 }
 
 template <typename T, int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<T>* lines = reinterpret_cast<Cx<T>*>(smem_raw);
-    const int rw = 1 << a.rw_log2;
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
     const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
-    const bool active = line < rw && j < a.m;
-    const int npairs = N / 2 + 1;
-    const size_t blk = (size_t)jb * (N + 1);
-    for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
-        const int jj = e & (rw - 1);
-        const int k = e >> a.rw_log2;
-        if ((jb << a.rw_log2) + jj >= a.m) continue;
-        Cx<T>* b = lines + (size_t)jj * N;
-        if (k == 0) {
-            const T x0 = a.spec[(blk + 0) * rw + jj].x * a.w_end;
-            const T xN = a.spec[(blk + N) * rw + jj].x * a.w_end;
-            b[0] = Cx<T>{x0 + xN, x0 - xN};
-            continue;
-        }
-        const Cx<T> xk = a.spec[(blk + k) * rw + jj] * a.w_mid;
-        const Cx<T> xn = a.spec[(blk + N - k) * rw + jj] * a.w_mid;
-        const Cx<T> P = xk + cconj(xn);
-        const Cx<T> Q = xk - cconj(xn);
-        const Cx<T> iWQ = mul_i(cmulc(Q, a.tw[k]));   // i conj(W) Q
-        b[k] = P + iWQ;
-        if (N - k != k) b[N - k] = cconj(P - iWQ);
-    }
+    const bool active = line < (1 << a.rw_log2) && j < a.m;
+    c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
     __syncthreads();
     fft_lds<T, true, EPT, RMAX>(lines + (size_t)line * N, a.fft, a.tw, t, a.nthr, active);
     if (active) {
@@ -123,6 +151,132 @@ __global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
             dst[i] = double2{(double)z.x * s, (double)z.y * s};
         }
     }
+}
+
+// ---------------------------------------------------------------- mixed lambda passes
+struct MixLambdaArgs {
+    const Cx<float>* s0;       // float32 spectrum of the first iterate
+    const Cx<float>* sd;       // float32 spectrum of the correction
+    Cx<double>* su;            // float64 spectrum written by k_lambda_mix
+    double* u;                 // output rows [m][n]
+    const Cx<float>* tw32;     // e^{-2 pi i t/n} (float32)
+    const Cx<double>* tw64;    // e^{-2 pi i t/n} (float64)
+    double* partial;           // per block: sum of correction^2 and of u^2 (or nullptr)
+    int n, m, N, rw_log2;
+    double inv_n;
+    FftDesc fft;
+    int nthr;
+    int accumulate;            // 1: u += correction (u already holds the previous iterate)
+};
+
+// Every thread holds at most this many line values while a line changes precision.
+template <int EPT, int RMAX>
+struct LineHold {
+    static constexpr int value = EPT > RMAX ? EPT : RMAX;
+};
+
+// u0 = inverse float32 DFT of s0 (per row), then the float64 forward DFT of u0
+// (no sin^2 scaling, weight 1/n) -> su.  LDS per row: N float64 complex values.
+template <int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Cx<double>* lines = reinterpret_cast<Cx<double>*>(smem_raw);
+    const int N = a.N;
+    const int line = threadIdx.x / a.nthr;
+    const int t = threadIdx.x - line * a.nthr;
+    const int jb = blockIdx.x;
+    const int j = (jb << a.rw_log2) + line;
+    const bool active = line < (1 << a.rw_log2) && j < a.m;
+    // float32 view: row r uses the first N float32 complex slots of its float64 line
+    Cx<float>* fl = reinterpret_cast<Cx<float>*>(lines);
+    c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
+    __syncthreads();
+    Cx<float>* fbuf = fl + (size_t)line * 2 * N;
+    fft_lds<float, true, EPT, RMAX>(fbuf, a.fft, a.tw32, t, a.nthr, active);
+    constexpr int H = LineHold<EPT, RMAX>::value;
+    Cx<float> hold[H];
+#pragma unroll
+    for (int e = 0; e < H; ++e) {
+        const int i = t + e * a.nthr;
+        if (active && i < N) hold[e] = fbuf[i];
+    }
+    __syncthreads();
+    Cx<double>* dbuf = lines + (size_t)line * N;
+#pragma unroll
+    for (int e = 0; e < H; ++e) {
+        const int i = t + e * a.nthr;
+        if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x, (double)hold[e].y};
+    }
+    __syncthreads();
+    fft_lds<double, false, EPT, RMAX>(dbuf, a.fft, a.tw64, t, a.nthr, active);
+    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.inv_n, a.inv_n);
+}
+
+// u = u0 + d (or u += d) with u0, d the float32 inverse DFTs of s0 and sd,
+// summed in float64.  Optionally accumulates per-block sums of d^2 and u^2.
+template <int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][16];
+    Cx<float>* fl = reinterpret_cast<Cx<float>*>(smem_raw);   // row r: [u0 line | d line]
+    const int N = a.N;
+    const int line = threadIdx.x / a.nthr;
+    const int t = threadIdx.x - line * a.nthr;
+    const int jb = blockIdx.x;
+    const int j = (jb << a.rw_log2) + line;
+    const bool active = line < (1 << a.rw_log2) && j < a.m;
+    const size_t stride = 2 * (size_t)N;
+    if (!a.accumulate) c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
+    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
+    __syncthreads();
+    Cx<float>* b0 = fl + (size_t)line * stride;
+    Cx<float>* b1 = b0 + N;
+    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(b0, a.fft, a.tw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(b1, a.fft, a.tw32, t, a.nthr, active);
+    double sd2 = 0.0, su2 = 0.0;
+    if (active) {
+        double2* dst = reinterpret_cast<double2*>(a.u + (size_t)j * a.n);
+        for (int i = t; i < N; i += a.nthr) {
+            const Cx<float> d = b1[i];
+            double2 base;
+            if (a.accumulate) base = dst[i];
+            else base = double2{(double)b0[i].x, (double)b0[i].y};
+            const double2 v = double2{base.x + (double)d.x, base.y + (double)d.y};
+            dst[i] = v;
+            sd2 += (double)d.x * d.x + (double)d.y * d.y;
+            su2 += v.x * v.x + v.y * v.y;
+        }
+    }
+    if (a.partial) {
+        for (int off = 32; off > 0; off >>= 1) {
+            sd2 += __shfl_down(sd2, off, 64);
+            su2 += __shfl_down(su2, off, 64);
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) { red[0][wave] = sd2; red[1][wave] = su2; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double x = 0.0, y = 0.0;
+            for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { x += red[0][w]; y += red[1][w]; }
+            a.partial[2 * blockIdx.x] = x;
+            a.partial[2 * blockIdx.x + 1] = y;
+        }
+    }
+}
+
+// Sum of the per-block partials (one block): out[0] = sum of d^2, out[1] = sum of u^2.
+__global__ void __launch_bounds__(256) k_reduce_partials(const double* partial, int nblk, double* out) {
+    __shared__ double r0[256], r1[256];
+    double x = 0.0, y = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) { x += partial[2 * b]; y += partial[2 * b + 1]; }
+    r0[threadIdx.x] = x;
+    r1[threadIdx.x] = y;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) { r0[threadIdx.x] += r0[threadIdx.x + h]; r1[threadIdx.x] += r1[threadIdx.x + h]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = r0[0]; out[1] = r1[0]; }
 }
 
 // ---------------------------------------------------------------- theta pass
@@ -587,6 +741,176 @@ __global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
         Cx<T> x = buf[pos] * invm;
         if (sine && (j & 1)) x = Cx<T>{-x.x, -x.y};
         a.spec[idx] = x;
+    }
+}
+
+// ---------------------------------------------------------------- mixed theta pass
+// Float32 bulk solve with float64 right-hand side / residual (iterative
+// refinement).  Wavenumbers k < k64 (always including k = 0) are eliminated in
+// float64: their systems are too ill-conditioned for float32 corrections.  RESID = false (first solve):
+//   load the float64 spectrum of sin^2 b, float64 cosine/sine analysis -> F
+//   (true coefficients, position order), store F in place of the input,
+//   solve (L - k^2) a = F in float32 (k = 0: float64 with the constraint),
+//   float32 synthesis -> float32 spectrum s0.
+// RESID = true (correction):
+//   load the float64 spectrum of the current iterate, float64 analysis -> X,
+//   r = F - (L - k^2) X in float64 (k = 0: constraint row r_0 = c0 - (X_0 +
+//   sum_{q>=2 even} X_q/(1 - q^2))), solve for the correction in float32
+//   (k = 0 float64), float32 synthesis -> float32 spectrum sd.
+constexpr int kThetaHold = 16;   // positions per thread in the residual / conversion loops
+
+struct ThetaMixArgs {
+    Cx<double>* sa;            // float64 spectrum of sin^2 b; replaced by F (position order)
+    const Cx<double>* su;      // RESID: float64 spectrum of the current iterate
+    Cx<float>* out;            // float32 spectrum written (s0 or sd)
+    const Cx<double>* tw64;
+    const Cx<double>* eq64;
+    const Cx<float>* tw32;
+    const Cx<float>* eq32;
+    int n, m, N, rw_log2;
+    FftDesc fft;
+    int nthr_fft;
+    int k8;
+    double c0;                 // integral / (4 pi)
+    const double* k0tab;
+    const double* fint_w;
+    double* fint_out;
+    int k64;                   // wavenumbers below this are eliminated in float64
+};
+
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID>
+__global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Cx<double> red[16];
+    Cx<double>* bufd = reinterpret_cast<Cx<double>*>(smem_raw);
+    Cx<float>* buff = reinterpret_cast<Cx<float>*>(smem_raw);
+    const int k = (blockIdx.x & 7) * a.k8 + (blockIdx.x >> 3);
+    if (k > a.N) return;
+    const int m = a.m, N = a.N, rwl = a.rw_log2, rw = 1 << rwl;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool sine = (k & 1) != 0;
+    const double invm = 1.0 / (double)m;
+    auto idx = [&](int j) -> size_t {
+        return ((((size_t)(j >> rwl)) * (N + 1) + k) << rwl) + (j & (rw - 1));
+    };
+    auto posj = [&](int j) -> int { return (j & 1) ? m - ((j + 1) >> 1) : (j >> 1); };
+
+    // float64 analysis of the input column
+    const Cx<double>* src = RESID ? a.su : a.sa;
+    double fpart = 0.0;
+    for (int j = tid; j < m; j += nthr) {
+        Cx<double> x = src[idx(j)];
+        if (sine && (j & 1)) x = Cx<double>{-x.x, -x.y};
+        bufd[posj(j)] = x;
+        if (!RESID && k == 0 && a.fint_w) fpart += a.fint_w[j] * x.x;
+    }
+    if (!RESID && k == 0 && a.fint_w) {
+        const Cx<double> sm = block_sum(Cx<double>{fpart, 0.0}, red);
+        if (tid == 0) *a.fint_out = sm.x;
+    }
+    __syncthreads();
+    fft_lds<double, false, EPT, RMAX>(bufd, a.fft, a.tw64, tid, a.nthr_fft, tid < a.nthr_fft);
+    for (int q = tid; q <= m / 2; q += nthr) {
+        const int qq = q == 0 ? 0 : m - q;
+        const Cx<double> A = bufd[q], B = bufd[qq];
+        const Cx<double> Eq = a.eq64[q];
+        const Cx<double> yq = (cmul(Eq, A) + cmulc(B, Eq)) * (0.5 * (q == 0 ? invm : 2.0 * invm));
+        if (qq != q) {
+            const Cx<double> Eqq = a.eq64[qq];
+            bufd[qq] = (cmul(Eqq, B) + cmulc(A, Eqq)) * invm;
+        }
+        bufd[q] = yq;
+    }
+    __syncthreads();
+
+    // right-hand side in position order, held in registers across the barrier
+    Cx<double> rh[kThetaHold];
+    double r0 = a.c0;
+    const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
+    if (!RESID) {
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) {
+                rh[e] = bufd[p];
+                a.sa[idx(p)] = rh[e];
+            }
+        }
+    } else {
+        Cx<double> part{0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) {
+                const int q = sine ? m - p : p;
+                if (k == 0 && q == 0) {
+                    rh[e] = Cx<double>{0.0, 0.0};
+                    continue;
+                }
+                double sub, diag, sup;
+                band<double>(q, k, q - 2 < qlo, q + 2 > qhi, false, sub, diag, sup);
+                Cx<double> ax = bufd[p] * diag;
+                if (q - 2 >= qlo) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
+                if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
+                rh[e] = a.sa[idx(p)] - ax;
+                if (k == 0 && (q & 1) == 0) part = part + bufd[p] * (1.0 / (1.0 - (double)q * (double)q));
+            }
+        }
+        if (k == 0) {
+            const Cx<double> dot = block_sum(part, red);
+            const Cx<double> x0 = bufd[0];
+            r0 = a.c0 - (x0.x + dot.x);   // the imaginary part of the k = 0 column is zero
+        }
+    }
+    __syncthreads();
+    const bool dbl = k < a.k64;   // ill-conditioned low wavenumbers (and k = 0) in float64
+#pragma unroll
+    for (int e = 0; e < kThetaHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) {
+            if (dbl) bufd[p] = rh[e];
+            else buff[p] = Cx<float>{(float)rh[e].x, (float)rh[e].y};
+        }
+    }
+    __syncthreads();
+    if (k == 0) solve_k0<double, SMAXD>(bufd, smem_raw, m, false, r0, a.k0tab, red, tid);
+    else if (dbl) solve_partitioned<double, SMAXD>(bufd, smem_raw, m, k, sine, false, tid);
+    else solve_partitioned<float, SMAXF>(buff, smem_raw, m, k, sine, false, tid);
+    __syncthreads();
+    if (dbl) {
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) rh[e] = bufd[p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) buff[p] = Cx<float>{(float)rh[e].x, (float)rh[e].y};
+        }
+        __syncthreads();
+    }
+    // float32 synthesis
+    const float fm = (float)m;
+    for (int q = tid; q <= m / 2; q += nthr) {
+        const int qq = q == 0 ? 0 : m - q;
+        const Cx<float> yq = buff[q] * (q == 0 ? fm : fm * 0.5f);
+        const Cx<float> yqq = buff[qq] * (fm * 0.5f);
+        if (q == 0) {
+            buff[0] = yq;
+        } else {
+            buff[q] = cmulc(yq - mul_i(yqq), a.eq32[q]);
+            if (qq != q) buff[qq] = cmulc(yqq - mul_i(yq), a.eq32[qq]);
+        }
+    }
+    __syncthreads();
+    fft_lds<float, true, EPT, RMAX>(buff, a.fft, a.tw32, tid, a.nthr_fft, tid < a.nthr_fft);
+    const float finvm = 1.0f / fm;
+    for (int j = tid; j < m; j += nthr) {
+        Cx<float> x = buff[posj(j)] * finvm;
+        if (sine && (j & 1)) x = Cx<float>{-x.x, -x.y};
+        a.out[idx(j)] = x;
     }
 }
 

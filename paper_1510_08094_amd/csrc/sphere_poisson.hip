@@ -144,6 +144,22 @@ KernelSet<T> pick_kernels(int rmax) {
     return rmax <= 16 ? kernel_set<T, 16>() : kernel_set<T, 32>();
 }
 
+struct MixedSet {
+    void (*theta_first)(sp::ThetaMixArgs);
+    void (*theta_resid)(sp::ThetaMixArgs);
+    void (*mix)(sp::MixLambdaArgs);
+    void (*update)(sp::MixLambdaArgs);
+};
+
+template <int RMAX>
+MixedSet mixed_set() {
+    return MixedSet{&sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false>,
+                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true>,
+                    &sp::k_lambda_mix<kEPT, RMAX>, &sp::k_lambda_update<kEPT, RMAX>};
+}
+
+MixedSet pick_mixed(int rmax) { return rmax <= 16 ? mixed_set<16>() : mixed_set<32>(); }
+
 template <typename T>
 struct Tables {
     Cx<T>* tw_n = nullptr;   // n entries
@@ -168,6 +184,7 @@ struct sp_plan_s {
     FftDesc fft_lam{}, fft_theta{};
     KernelSet<double> kd{};
     KernelSet<float> kf{};
+    MixedSet km{};
     // device memory
     void* block = nullptr;    // one allocation holding everything below
     size_t block_bytes = 0;
@@ -177,8 +194,13 @@ struct sp_plan_s {
     double* sin2 = nullptr;
     double* k0tab = nullptr;
     double* fint_w = nullptr;
-    double* scal = nullptr;   // device scalars: [0] = integral of f
+    double* scal = nullptr;   // device scalars: [0] = integral of f, [1..2] = sum d^2, sum u^2
     size_t spec_elems = 0;
+    // MIXED workspace
+    Cx<double>* specB = nullptr;   // float64 spectrum of the current iterate
+    Cx<float>* spec0 = nullptr;    // float32 spectrum of the first iterate
+    Cx<float>* specd = nullptr;    // float32 spectrum of the correction
+    double* partial = nullptr;     // per lambda block: sum d^2, sum u^2
     // profiling: event pairs around launches
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
@@ -220,10 +242,11 @@ int validate_desc(const sp_desc* d) {
 struct Layout {
     size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
+    size_t off_specB, off_spec0, off_specd, off_partial;
     size_t spec_elems;
 };
 
-Layout layout_for(int n, int m, int rw) {
+Layout layout_for(int n, int m, int rw, bool mixed) {
     Layout L{};
     size_t N = n / 2;
     size_t nblk = (size_t)(m + rw - 1) / rw;
@@ -241,6 +264,12 @@ Layout layout_for(int n, int m, int rw) {
     L.off_k0 = take((size_t)2 * (m + 2) * sizeof(double));
     L.off_fint = take((size_t)m * sizeof(double));
     L.off_scal = take(16 * sizeof(double));
+    if (mixed) {
+        L.off_specB = take(L.spec_elems * sizeof(Cx<double>));
+        L.off_spec0 = take(L.spec_elems * sizeof(Cx<float>));
+        L.off_specd = take(L.spec_elems * sizeof(Cx<float>));
+        L.off_partial = take(2 * nblk * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -306,7 +335,7 @@ extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
     int rwl = 0, nt = 0;
     size_t lds = 0;
     if (!lambda_schedule(d->n_lambda / 2, d->m_theta, rl, 160 * 1024, &rwl, &nt, &lds)) return 0;
-    return layout_for(d->n_lambda, d->m_theta, 1 << rwl).total;
+    return layout_for(d->n_lambda, d->m_theta, 1 << rwl, d->precision == SP_MIXED).total;
 }
 
 extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_stream) {
@@ -314,10 +343,6 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     *out = nullptr;
     int st = validate_desc(d);
     if (st != SP_OK) return st;
-    if (d->precision != SP_FP64) {
-        g_hip_err = "the mixed-precision path is not built yet";
-        return SP_ERR_INVALID_ARG;
-    }
     int dev = 0;
     size_t lds_limit = 0;
     st = query_device(&dev, &lds_limit);
@@ -348,7 +373,8 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     }
     p->theta_fft_threads = fft_threads(rt, m);
     int ptotD = solve_threads(m, kSmaxD), ptotF = solve_threads(m, kSmaxF);
-    p->theta_threads = round_up(std::max(p->theta_fft_threads, std::max(ptotD, ptotF)), 64);
+    p->theta_threads = round_up(std::max(std::max(p->theta_fft_threads, ceil_div(m, sp::kThetaHold)),
+                                         std::max(ptotD, ptotF)), 64);
     p->theta_lds64 = theta_lds_bytes<double>(m, ptotD);
     p->theta_lds32 = theta_lds_bytes<float>(m, ptotF);
     const size_t static_lds = 16 * sizeof(Cx<double>);
@@ -359,10 +385,18 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     p->k8 = (N + 1 + 7) / 8;
     p->kd = pick_kernels<double>(p->rmax);
     p->kf = pick_kernels<float>(p->rmax);
+    p->km = pick_mixed(p->rmax);
     set_lds_attr(p->kd, p->lam_lds, p->theta_lds64);
+    set_lds_attr(p->kf, p->lam_lds, p->theta_lds64);
+    for (const void* fn : {(const void*)p->km.theta_first, (const void*)p->km.theta_resid})
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
+    for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
+    (void)hipGetLastError();
 
     // ---- device memory
-    Layout L = layout_for(n, m, 1 << p->rw_log2);
+    const bool mixed = d->precision == SP_MIXED;
+    Layout L = layout_for(n, m, 1 << p->rw_log2, mixed);
     p->spec_elems = L.spec_elems;
     hipError_t e = hipMalloc(&p->block, L.total);
     if (e != hipSuccess) {
@@ -383,6 +417,12 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     p->k0tab = (double*)(b + L.off_k0);
     p->fint_w = (double*)(b + L.off_fint);
     p->scal = (double*)(b + L.off_scal);
+    if (mixed) {
+        p->specB = (Cx<double>*)(b + L.off_specB);
+        p->spec0 = (Cx<float>*)(b + L.off_spec0);
+        p->specd = (Cx<float>*)(b + L.off_specd);
+        p->partial = (double*)(b + L.off_partial);
+    }
 
     // ---- host tables
     std::vector<Cx<double>> twn(n), twm(m), eq(m);
@@ -563,7 +603,7 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     else { la.w_mid = 2.0; la.w_end = 1.0; }
     {
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
-        hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
     }
     // theta
     sp::ThetaArgs<double> ta{};
@@ -588,27 +628,109 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     else { la.w_mid = 0.5; la.w_end = 1.0; la.out_scale = 1.0 / n; la.rowscale = p->sin2; }
     {
         ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
-        hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(rw * p->lam_threads), p->lam_lds, s, la);
+        hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return SP_OK;
 }
 
-int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status) {
+int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status, int iters) {
     if (!(p->desc.flags & SP_SYNC_INFO)) return status;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    double fint = 0.0;
-    e = hipMemcpy(&fint, p->scal, sizeof(double), hipMemcpyDeviceToHost);
+    double sc[3] = {0.0, 0.0, 0.0};
+    e = hipMemcpy(sc, p->scal, sizeof(sc), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy info");
+    double rel = 0.0;
+    if (iters > 0) rel = sc[2] > 0.0 ? std::sqrt(sc[1] / sc[2]) : 0.0;
+    if (iters > 0 && p->desc.tol > 0.0 && !(rel <= p->desc.tol)) status = SP_ERR_NOT_CONVERGED;
+    if (p->desc.precision == SP_MIXED && iters == 0 && p->desc.tol > 0.0) status = SP_ERR_NOT_CONVERGED;
     if (info) {
-        info->iters = 0;
-        info->rel_correction = 0.0;
-        info->f_integral = fint;
+        info->iters = iters;
+        info->rel_correction = rel;
+        info->f_integral = sc[0];
         info->status = status;
     }
     return status;
+}
+
+// MIXED: float64 right-hand side transform, float32 bulk solve, `max_refine`
+// float64-residual corrections (see the mixed kernels).
+int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
+    const int n = p->n, m = p->m, N = p->N;
+    const int rw = 1 << p->rw_log2;
+    const int nblk = (m + rw - 1) / rw;
+    const bool want = (p->desc.flags & SP_SYNC_INFO) != 0;
+    const dim3 lam_grid(nblk), lam_block(round_up(rw * p->lam_threads, 64));
+    const dim3 th_grid(8 * p->k8), th_block(p->theta_threads);
+    // 1. float64 lambda transform of sin^2 f -> spec64
+    sp::LambdaArgs<double> la{};
+    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.rowscale = p->sin2;
+    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.fft = p->fft_lam; la.nthr = p->lam_threads;
+    la.w_mid = 1.0 / n; la.w_end = 1.0 / n;
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+        hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
+    }
+    // 2. first solve
+    sp::ThetaMixArgs ta{};
+    ta.sa = p->spec64; ta.su = p->specB; ta.out = p->spec0;
+    ta.tw64 = p->t64.tw_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.tw_m; ta.eq32 = p->t32.eq;
+    ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2; ta.fft = p->fft_theta;
+    ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
+    ta.fint_w = p->fint_w; ta.fint_out = p->scal;
+    ta.k64 = p->desc.low_k_fp64 < 0 ? std::max(16, m / 64) : std::max(1, p->desc.low_k_fp64);
+    {
+        ProfScope ps(p, SP_KERNEL_THETA, s);
+        hipLaunchKernelGGL(p->km.theta_first, th_grid, th_block, p->theta_lds64, s, ta);
+    }
+    const int R = p->desc.max_refine;
+    if (R == 0) {
+        sp::LambdaArgs<float> lf{};
+        lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.rowscale = nullptr;
+        lf.n = n; lf.m = m; lf.N = N; lf.rw_log2 = p->rw_log2; lf.fft = p->fft_lam; lf.nthr = p->lam_threads;
+        lf.w_mid = 1.0f; lf.w_end = 1.0f; lf.out_scale = 1.0;
+        ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
+        hipLaunchKernelGGL(p->kf.inv, lam_grid, lam_block, p->lam_lds, s, lf);
+    } else {
+        sp::MixLambdaArgs ma{};
+        ma.s0 = p->spec0; ma.sd = p->specd; ma.su = p->specB; ma.u = u;
+        ma.tw32 = p->t32.tw_n; ma.tw64 = p->t64.tw_n; ma.partial = want ? p->partial : nullptr;
+        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2; ma.inv_n = 1.0 / n;
+        ma.fft = p->fft_lam; ma.nthr = p->lam_threads; ma.accumulate = 0;
+        {
+            ProfScope ps(p, SP_KERNEL_LAMBDA_MIX, s);
+            hipLaunchKernelGGL(p->km.mix, lam_grid, lam_block, p->lam_lds, s, ma);
+        }
+        ta.out = p->specd;
+        ta.fint_w = nullptr;
+        for (int it = 1; it <= R; ++it) {
+            if (it > 1) {
+                // float64 lambda transform of the current iterate (no sin^2) -> specB
+                la.x = u; la.spec = p->specB; la.rowscale = nullptr;
+                ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+                hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
+            }
+            {
+                ProfScope ps(p, SP_KERNEL_THETA_RESID, s);
+                hipLaunchKernelGGL(p->km.theta_resid, th_grid, th_block, p->theta_lds64, s, ta);
+            }
+            ma.accumulate = it > 1 ? 1 : 0;
+            {
+                ProfScope ps(p, SP_KERNEL_LAMBDA_UPD, s);
+                hipLaunchKernelGGL(p->km.update, lam_grid, lam_block, p->lam_lds, s, ma);
+            }
+        }
+        if (want) {
+            ProfScope ps(p, SP_KERNEL_REDUCE, s);
+            hipLaunchKernelGGL(sp::k_reduce_partials, dim3(1), dim3(256), 0, s, (const double*)p->partial, nblk,
+                               p->scal + 1);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
 }
 
 }  // namespace
@@ -621,9 +743,14 @@ extern "C" int sphere_poisson_solve(sp_plan p, const double* f, double* u, doubl
     if (overlap(f, u, bytes)) return SP_ERR_ALIAS;
     hipStream_t s = (hipStream_t)hip_stream;
     const double PI = 3.14159265358979323846;
+    if (p->desc.precision == SP_MIXED) {
+        int st = run_mixed(p, f, u, integral / (4.0 * PI), s);
+        if (st != SP_OK) return st;
+        return finish_info(p, s, info, SP_OK, p->desc.max_refine);
+    }
     int st = run_fp64(p, f, u, sp::kSolve, integral / (4.0 * PI), true, false, true, s);
     if (st != SP_OK) return st;
-    return finish_info(p, s, info, SP_OK);
+    return finish_info(p, s, info, SP_OK, 0);
 }
 
 extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* fbar, void* hip_stream,
@@ -635,7 +762,7 @@ extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* 
     hipStream_t s = (hipStream_t)hip_stream;
     int st = run_fp64(p, g, fbar, sp::kSolveTransposed, 0.0, false, true, false, s);
     if (st != SP_OK) return st;
-    return finish_info(p, s, info, SP_OK);
+    return finish_info(p, s, info, SP_OK, 0);
 }
 
 extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, double* out, void* hip_stream) {

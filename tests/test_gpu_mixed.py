@@ -1,0 +1,111 @@
+"""MIXED precision (float32 transforms and banded solves, float64 residual,
+update and k = 0 system) against the float64 oracle: relative 2-norm error
+<= 1e-10 after the refinement step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import sh_inputs as S
+from conftest import rel2
+
+pytestmark = pytest.mark.gpu
+
+TOL_MIXED = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1510_08094_amd as P
+    assert torch.cuda.is_available(), "no GPU"
+    P.library()
+    return P
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def run(P, f, integral=0.0, **kw):
+    m, n = f.shape
+    plan = P.SpherePoisson(n, m, "mixed", **kw)
+    u = host(plan.solve(gpu(f), integral))
+    info = plan.info
+    plan.close()
+    return u, info
+
+
+@pytest.mark.parametrize("n,m", [(64, 64), (4, 4), (40, 21), (150, 75), (210, 143), (62, 31),
+                                 (128, 2048), (2048, 128), (1984, 1984), (1024, 1024)])
+def test_mixed_matches_oracle(P, n, m):
+    print("mixed", n, m, flush=True)
+    L = max(1, min(n // 2 - 1, m - 3, 40))
+    f = S.sphere_field(21, 0, n, m, L) + 1e-3 * np.random.default_rng(n + m).standard_normal((m, n))
+    u, _ = run(P, f)
+    assert rel2(u, O.solve_reduced(f)) <= TOL_MIXED
+
+
+def test_mixed_c1_closed_form(P):
+    f, u_exact = S.sphere_field(1, 0, 1024, 1024, 256, with_solution=True)
+    u, _ = run(P, f)
+    assert rel2(u, u_exact) <= TOL_MIXED
+    assert rel2(u, O.solve_reduced(f)) <= TOL_MIXED
+
+
+def test_mixed_without_refinement_is_float32_accurate(P):
+    """max_refine = 0 returns the float32 solve (about 1e-7) and, with a
+    tolerance, reports SP_ERR_NOT_CONVERGED."""
+    f = S.sphere_field(22, 0, 256, 192, 60)
+    plan = P.SpherePoisson(256, 192, "mixed", max_refine=0, tol=1e-10, sync_info=True)
+    with pytest.raises(P.SpError) as e:
+        plan.solve(gpu(f))
+    assert e.value.code == 5
+    plan.close()
+    u, _ = run(P, f, max_refine=0)
+    err = rel2(u, O.solve_reduced(f))
+    assert 1e-9 < err < 1e-5
+
+
+def test_mixed_info_and_two_corrections(P):
+    f = S.sphere_field(23, 0, 512, 384, 120)
+    ref = O.solve_reduced(f)
+    u1, i1 = run(P, f, max_refine=1, tol=1e-6, sync_info=True)
+    u2, i2 = run(P, f, max_refine=2, tol=1e-10, sync_info=True)
+    assert i1.iters == 1 and i2.iters == 2 and i1.status == 0 and i2.status == 0
+    assert 1e-9 < i1.rel_correction < 1e-5          # the first correction is float32-sized
+    assert i2.rel_correction < 1e-10 and i2.rel_correction < 1e-2 * i1.rel_correction
+    assert rel2(u1, ref) <= TOL_MIXED and rel2(u2, ref) <= TOL_MIXED
+
+
+@pytest.mark.parametrize("c", [0.0, 2.0])
+def test_mixed_integral_constraint(P, c):
+    f, u_exact = S.sphere_field(24, 0, 96, 64, 20, with_solution=True)
+    u, _ = run(P, f, integral=c)
+    assert rel2(u, u_exact + c / (4 * np.pi)) <= TOL_MIXED
+
+
+def test_mixed_float32_elimination_everywhere_needs_two_corrections(P):
+    """With every k > 0 eliminated in float32 the correction of the
+    ill-conditioned low wavenumbers is poor; two corrections still reach the bar."""
+    f = S.sphere_field(25, 0, 2048, 4096, 800)
+    u, info = run(P, f, max_refine=2, low_k_fp64=1, sync_info=True)
+    assert info.iters == 2
+    assert rel2(u, O.solve_reduced(f)) <= TOL_MIXED
+
+
+def test_mixed_c2(P):
+    """10000 x 10000, l <= 2000: the headline workload, against the closed form and the oracle."""
+    print("c2 synth", flush=True)
+    f, u_exact = S.sphere_field(2, 0, 10000, 10000, 2000, with_solution=True)
+    print("c2 gpu", flush=True)
+    u, _ = run(P, f)
+    e = rel2(u, u_exact)
+    print("c2 mixed rel err vs closed form", e, flush=True)
+    assert e <= TOL_MIXED
+    del u_exact
+    assert rel2(u, O.solve_reduced(f)) <= TOL_MIXED
