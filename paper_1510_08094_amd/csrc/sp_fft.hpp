@@ -225,7 +225,7 @@ struct FftDesc {
     int N;                 // transform length
     int npass;
     int radix[kMaxPass];
-    int tw_stride;         // tw[t * tw_stride] = e^{-2 pi i t / N}
+    int tw_off[kMaxPass];  // offset of each pass's twiddles in the per-pass table
 };
 
 // Butterflies each thread owns in a radix-R pass when a thread holds at most
@@ -242,9 +242,11 @@ struct Bpt {
 //   butterfly j (0 <= j < N/R), k = j mod Ns:
 //     v_r = buf[j + r N/R] * w^{r k},  w = e^{-+2 pi i / (Ns R)}
 //     V = DFT_R(v);  buf[(j - k) R + k + r Ns] = V_r
+// The pass's twiddles are stored as tw[(r - 1) Ns + k] = e^{-2 pi i r k/(Ns R)},
+// so neighbouring lanes (neighbouring k) read neighbouring entries.
 template <typename T, int R, bool INV, int EPT>
 __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, int Ns,
-                                              const Cx<T>* __restrict__ tw, int tw_stride,
+                                              const Cx<T>* __restrict__ tw,
                                               int t, int nthr, bool active) {
     constexpr int B = Bpt<R, EPT>::value;
     const int nb = N / R;
@@ -261,17 +263,15 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
     }
     __syncthreads();
     if (active) {
-        const int span = N / (Ns * R);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + b * nthr;
             if (j < nb) {
                 const int k = j % Ns;
-                if (k != 0) {
-                    const int step = span * k * tw_stride;
+                if (Ns > 1) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
-                        const Cx<T> w = tw[r * step];
+                        const Cx<T> w = tw[(r - 1) * Ns + k];
                         v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
                     }
                 }
@@ -289,28 +289,29 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
 // radices compiled into this instantiation.
 template <typename T, bool INV, int EPT, int RMAX>
 __device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ buf, const FftDesc& d,
-                                        const Cx<T>* __restrict__ tw, int t, int nthr, bool active) {
+                                        const Cx<T>* __restrict__ ptw, int t, int nthr, bool active) {
     int Ns = 1;
     for (int p = 0; p < d.npass; ++p) {
         const int R = d.radix[p];
+        const Cx<T>* tw = ptw + d.tw_off[p];
         switch (R) {
-            case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 4: stockham_pass<T, 4, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 5: stockham_pass<T, 5, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 7: stockham_pass<T, 7, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 8: stockham_pass<T, 8, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 11: stockham_pass<T, 11, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 13: stockham_pass<T, 13, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-            case 16: stockham_pass<T, 16, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+            case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 4: stockham_pass<T, 4, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 5: stockham_pass<T, 5, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 7: stockham_pass<T, 7, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 8: stockham_pass<T, 8, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 11: stockham_pass<T, 11, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 13: stockham_pass<T, 13, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+            case 16: stockham_pass<T, 16, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
             default:
                 if constexpr (RMAX >= 17) {
                     switch (R) {
-                        case 17: stockham_pass<T, 17, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-                        case 19: stockham_pass<T, 19, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-                        case 23: stockham_pass<T, 23, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-                        case 29: stockham_pass<T, 29, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
-                        case 31: stockham_pass<T, 31, INV, EPT>(buf, d.N, Ns, tw, d.tw_stride, t, nthr, active); break;
+                        case 17: stockham_pass<T, 17, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                        case 19: stockham_pass<T, 19, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                        case 23: stockham_pass<T, 23, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                        case 29: stockham_pass<T, 29, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                        case 31: stockham_pass<T, 31, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
                         default: break;
                     }
                 }

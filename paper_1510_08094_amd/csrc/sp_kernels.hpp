@@ -26,7 +26,8 @@ struct LambdaArgs {
     const double* x;        // forward: input rows [m][n]
     double* y;              // inverse: output rows [m][n]
     Cx<T>* spec;            // spectrum (forward: written; inverse: read)
-    const Cx<T>* tw;        // e^{-2 pi i t/n}, t = 0..n-1 (the length-N DFT uses stride 2)
+    const Cx<T>* tw;        // e^{-2 pi i t/n}, t = 0..n-1 (real-spectrum split)
+    const Cx<T>* ptw;       // per-pass twiddles of the length-N complex DFT
     const double* rowscale; // per-row multiplier or nullptr
     int n, m, N, rw_log2;
     T w_mid, w_end;         // forward: output weight for 0<k<N and for k in {0,N}; inverse: input weights
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
         }
     }
     __syncthreads();
-    fft_lds<T, false, EPT, RMAX>(buf, a.fft, a.tw, t, a.nthr, active);
+    fft_lds<T, false, EPT, RMAX>(buf, a.fft, a.ptw, t, a.nthr, active);
     r2c_split_store<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
 }
 
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
     __syncthreads();
-    fft_lds<T, true, EPT, RMAX>(lines + (size_t)line * N, a.fft, a.tw, t, a.nthr, active);
+    fft_lds<T, true, EPT, RMAX>(lines + (size_t)line * N, a.fft, a.ptw, t, a.nthr, active);
     if (active) {
         const Cx<T>* buf = lines + (size_t)line * N;
         const double s = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
@@ -161,6 +162,8 @@ struct MixLambdaArgs {
     double* u;                 // output rows [m][n]
     const Cx<float>* tw32;     // e^{-2 pi i t/n} (float32)
     const Cx<double>* tw64;    // e^{-2 pi i t/n} (float64)
+    const Cx<float>* ptw32;    // per-pass twiddles of the length-N DFT (float32)
+    const Cx<double>* ptw64;   // per-pass twiddles of the length-N DFT (float64)
     double* partial;           // per block: sum of correction^2 and of u^2 (or nullptr)
     int n, m, N, rw_log2;
     double inv_n;
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
     __syncthreads();
     Cx<float>* fbuf = fl + (size_t)line * 2 * N;
-    fft_lds<float, true, EPT, RMAX>(fbuf, a.fft, a.tw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(fbuf, a.fft, a.ptw32, t, a.nthr, active);
     constexpr int H = LineHold<EPT, RMAX>::value;
     Cx<float> hold[H];
 #pragma unroll
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
         if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x, (double)hold[e].y};
     }
     __syncthreads();
-    fft_lds<double, false, EPT, RMAX>(dbuf, a.fft, a.tw64, t, a.nthr, active);
+    fft_lds<double, false, EPT, RMAX>(dbuf, a.fft, a.ptw64, t, a.nthr, active);
     r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.inv_n, a.inv_n);
 }
 
@@ -231,8 +234,8 @@ __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
     __syncthreads();
     Cx<float>* b0 = fl + (size_t)line * stride;
     Cx<float>* b1 = b0 + N;
-    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(b0, a.fft, a.tw32, t, a.nthr, active);
-    fft_lds<float, true, EPT, RMAX>(b1, a.fft, a.tw32, t, a.nthr, active);
+    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(b0, a.fft, a.ptw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(b1, a.fft, a.ptw32, t, a.nthr, active);
     double sd2 = 0.0, su2 = 0.0;
     if (active) {
         double2* dst = reinterpret_cast<double2*>(a.u + (size_t)j * a.n);
@@ -301,7 +304,7 @@ enum ThetaMode { kSolve = 0, kSolveTransposed = 1, kTransformOnly = 2 };
 template <typename T>
 struct ThetaArgs {
     Cx<T>* spec;
-    const Cx<T>* tw;        // e^{-2 pi i t/m}, t = 0..m-1
+    const Cx<T>* tw;        // per-pass twiddles of the length-m complex DFT
     const Cx<T>* eq;        // e^{-i pi q/(2m)}, q = 0..m-1
     int n, m, N, rw_log2;
     FftDesc fft;
@@ -763,7 +766,7 @@ struct ThetaMixArgs {
     Cx<double>* sa;            // float64 spectrum of sin^2 b; replaced by F (position order)
     const Cx<double>* su;      // RESID: float64 spectrum of the current iterate
     Cx<float>* out;            // float32 spectrum written (s0 or sd)
-    const Cx<double>* tw64;
+    const Cx<double>* tw64;    // per-pass twiddles of the length-m DFT
     const Cx<double>* eq64;
     const Cx<float>* tw32;
     const Cx<float>* eq32;

@@ -91,12 +91,28 @@ int fft_threads(const std::vector<int>& rad, int L) {
     return t;
 }
 
-FftDesc make_desc(const std::vector<int>& rad, int L, int tw_stride) {
+// Per-pass twiddle table of a Stockham DFT of length L: pass p (radix R, span
+// Ns = product of earlier radices) stores e^{-2 pi i r k / (Ns R)} at
+// off_p + (r - 1) Ns + k, r = 1..R-1, k = 0..Ns-1.
+FftDesc make_desc(const std::vector<int>& rad, int L, std::vector<Cx<double>>* table) {
     FftDesc d{};
     d.N = L;
     d.npass = (int)rad.size();
-    for (size_t i = 0; i < rad.size(); ++i) d.radix[i] = rad[i];
-    d.tw_stride = tw_stride;
+    table->clear();
+    long long Ns = 1;
+    for (size_t i = 0; i < rad.size(); ++i) {
+        const int R = rad[i];
+        d.radix[i] = R;
+        d.tw_off[i] = (int)table->size();
+        for (int r = 1; r < R; ++r)
+            for (long long k = 0; k < Ns; ++k) {
+                Cx<double> w;
+                cis_neg((long long)r * k, Ns * R, &w.x, &w.y);
+                table->push_back(w);
+            }
+        Ns *= R;
+    }
+    if (table->empty()) table->push_back(Cx<double>{1.0, 0.0});
     return d;
 }
 
@@ -162,9 +178,10 @@ MixedSet pick_mixed(int rmax) { return rmax <= 16 ? mixed_set<16>() : mixed_set<
 
 template <typename T>
 struct Tables {
-    Cx<T>* tw_n = nullptr;   // n entries
-    Cx<T>* tw_m = nullptr;   // m entries
-    Cx<T>* eq = nullptr;     // m entries
+    Cx<T>* tw_n = nullptr;   // n entries: e^{-2 pi i t/n}
+    Cx<T>* pass_n = nullptr; // per-pass twiddles of the length-n/2 DFT
+    Cx<T>* pass_m = nullptr; // per-pass twiddles of the length-m DFT
+    Cx<T>* eq = nullptr;     // m entries: e^{-i pi q/(2m)}
 };
 
 }  // namespace
@@ -240,7 +257,7 @@ int validate_desc(const sp_desc* d) {
 }
 
 struct Layout {
-    size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32;
+    size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32, off_p64n, off_p32n;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
     size_t off_specB, off_spec0, off_specd, off_partial;
     size_t spec_elems;
@@ -260,6 +277,8 @@ Layout layout_for(int n, int m, int rw, bool mixed) {
     L.off_tw32n = take((size_t)n * sizeof(Cx<float>));
     L.off_tw32m = take((size_t)m * sizeof(Cx<float>));
     L.off_eq32 = take((size_t)m * sizeof(Cx<float>));
+    L.off_p64n = take((size_t)n * sizeof(Cx<double>));
+    L.off_p32n = take((size_t)n * sizeof(Cx<float>));
     L.off_sin2 = take((size_t)m * sizeof(double));
     L.off_k0 = take((size_t)2 * (m + 2) * sizeof(double));
     L.off_fint = take((size_t)m * sizeof(double));
@@ -364,8 +383,9 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     p->rmax = 1;
     for (int r : rl) p->rmax = std::max(p->rmax, r);
     for (int r : rt) p->rmax = std::max(p->rmax, r);
-    p->fft_lam = make_desc(rl, N, 2);
-    p->fft_theta = make_desc(rt, m, 1);
+    std::vector<Cx<double>> ptab_n, ptab_m;
+    p->fft_lam = make_desc(rl, N, &ptab_n);
+    p->fft_theta = make_desc(rt, m, &ptab_m);
 
     if (!lambda_schedule(N, m, rl, lds_limit, &p->rw_log2, &p->lam_threads, &p->lam_lds)) {
         delete p;
@@ -408,11 +428,13 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     unsigned char* b = (unsigned char*)p->block;
     p->spec64 = (Cx<double>*)(b + L.off_spec);
     p->t64.tw_n = (Cx<double>*)(b + L.off_tw64n);
-    p->t64.tw_m = (Cx<double>*)(b + L.off_tw64m);
+    p->t64.pass_m = (Cx<double>*)(b + L.off_tw64m);
     p->t64.eq = (Cx<double>*)(b + L.off_eq64);
     p->t32.tw_n = (Cx<float>*)(b + L.off_tw32n);
-    p->t32.tw_m = (Cx<float>*)(b + L.off_tw32m);
+    p->t32.pass_m = (Cx<float>*)(b + L.off_tw32m);
     p->t32.eq = (Cx<float>*)(b + L.off_eq32);
+    p->t64.pass_n = (Cx<double>*)(b + L.off_p64n);
+    p->t32.pass_n = (Cx<float>*)(b + L.off_p32n);
     p->sin2 = (double*)(b + L.off_sin2);
     p->k0tab = (double*)(b + L.off_k0);
     p->fint_w = (double*)(b + L.off_fint);
@@ -425,14 +447,15 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     }
 
     // ---- host tables
-    std::vector<Cx<double>> twn(n), twm(m), eq(m);
-    std::vector<Cx<float>> twn32(n), twm32(m), eq32(m);
+    std::vector<Cx<double>> twn(n), eq(m);
     for (int t = 0; t < n; ++t) cis_neg(t, n, &twn[t].x, &twn[t].y);
-    for (int t = 0; t < m; ++t) cis_neg(t, m, &twm[t].x, &twm[t].y);
     for (int t = 0; t < m; ++t) cis_neg(t, 4LL * m, &eq[t].x, &eq[t].y);
-    for (int t = 0; t < n; ++t) twn32[t] = Cx<float>{(float)twn[t].x, (float)twn[t].y};
-    for (int t = 0; t < m; ++t) twm32[t] = Cx<float>{(float)twm[t].x, (float)twm[t].y};
-    for (int t = 0; t < m; ++t) eq32[t] = Cx<float>{(float)eq[t].x, (float)eq[t].y};
+    auto to32 = [](const std::vector<Cx<double>>& v) {
+        std::vector<Cx<float>> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = Cx<float>{(float)v[i].x, (float)v[i].y};
+        return o;
+    };
+    std::vector<Cx<float>> twn32 = to32(twn), eq32 = to32(eq), pn32 = to32(ptab_n), pm32 = to32(ptab_m);
     const long double PI = 3.141592653589793238462643383279502884L;
     std::vector<double> sin2(m), fint(m);
     for (int j = 0; j < m; ++j) {
@@ -478,11 +501,13 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     };
     hipError_t ee = hipSuccess;
     if (ee == hipSuccess) ee = up(p->t64.tw_n, twn.data(), n * sizeof(Cx<double>));
-    if (ee == hipSuccess) ee = up(p->t64.tw_m, twm.data(), m * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t64.pass_m, ptab_m.data(), ptab_m.size() * sizeof(Cx<double>));
     if (ee == hipSuccess) ee = up(p->t64.eq, eq.data(), m * sizeof(Cx<double>));
     if (ee == hipSuccess) ee = up(p->t32.tw_n, twn32.data(), n * sizeof(Cx<float>));
-    if (ee == hipSuccess) ee = up(p->t32.tw_m, twm32.data(), m * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->t32.pass_m, pm32.data(), pm32.size() * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->t32.eq, eq32.data(), m * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->t64.pass_n, ptab_n.data(), ptab_n.size() * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t32.pass_n, pn32.data(), pn32.size() * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->sin2, sin2.data(), m * sizeof(double));
     if (ee == hipSuccess) ee = up(p->k0tab, k0.data(), k0.size() * sizeof(double));
     if (ee == hipSuccess) ee = up(p->fint_w, fint.data(), m * sizeof(double));
@@ -594,6 +619,7 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     la.y = out;
     la.spec = p->spec64;
     la.tw = p->t64.tw_n;
+    la.ptw = p->t64.pass_n;
     la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2;
     la.fft = p->fft_lam;
     la.nthr = p->lam_threads;
@@ -608,7 +634,7 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     // theta
     sp::ThetaArgs<double> ta{};
     ta.spec = p->spec64;
-    ta.tw = p->t64.tw_m;
+    ta.tw = p->t64.pass_m;
     ta.eq = p->t64.eq;
     ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2;
     ta.fft = p->fft_theta;
@@ -666,7 +692,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     const dim3 th_grid(8 * p->k8), th_block(p->theta_threads);
     // 1. float64 lambda transform of sin^2 f -> spec64
     sp::LambdaArgs<double> la{};
-    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.rowscale = p->sin2;
+    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n; la.rowscale = p->sin2;
     la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.fft = p->fft_lam; la.nthr = p->lam_threads;
     la.w_mid = 1.0 / n; la.w_end = 1.0 / n;
     {
@@ -676,7 +702,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     // 2. first solve
     sp::ThetaMixArgs ta{};
     ta.sa = p->spec64; ta.su = p->specB; ta.out = p->spec0;
-    ta.tw64 = p->t64.tw_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.tw_m; ta.eq32 = p->t32.eq;
+    ta.tw64 = p->t64.pass_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.pass_m; ta.eq32 = p->t32.eq;
     ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2; ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
     ta.fint_w = p->fint_w; ta.fint_out = p->scal;
@@ -688,7 +714,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     const int R = p->desc.max_refine;
     if (R == 0) {
         sp::LambdaArgs<float> lf{};
-        lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.rowscale = nullptr;
+        lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.ptw = p->t32.pass_n; lf.rowscale = nullptr;
         lf.n = n; lf.m = m; lf.N = N; lf.rw_log2 = p->rw_log2; lf.fft = p->fft_lam; lf.nthr = p->lam_threads;
         lf.w_mid = 1.0f; lf.w_end = 1.0f; lf.out_scale = 1.0;
         ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
@@ -697,6 +723,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
         sp::MixLambdaArgs ma{};
         ma.s0 = p->spec0; ma.sd = p->specd; ma.su = p->specB; ma.u = u;
         ma.tw32 = p->t32.tw_n; ma.tw64 = p->t64.tw_n; ma.partial = want ? p->partial : nullptr;
+        ma.ptw32 = p->t32.pass_n; ma.ptw64 = p->t64.pass_n;
         ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2; ma.inv_n = 1.0 / n;
         ma.fft = p->fft_lam; ma.nthr = p->lam_threads; ma.accumulate = 0;
         {
