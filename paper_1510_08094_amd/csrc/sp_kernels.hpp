@@ -165,8 +165,12 @@ struct MixLambdaArgs {
     const Cx<float>* ptw32;    // per-pass twiddles of the length-N DFT (float32)
     const Cx<double>* ptw64;   // per-pass twiddles of the length-N DFT (float64)
     double* partial;           // per block: sum of correction^2 and of u^2 (or nullptr)
+    const double* rowscale;    // update: per-row output multiplier (or nullptr)
     int n, m, N, rw_log2;
-    double inv_n;
+    float in_w_mid, in_w_end;  // weights of the float32 spectra read by the inverse DFTs
+    double mid_scale;          // mix: multiplier of the float32 inverse DFT before the float64 forward DFT
+    double out_w_mid, out_w_end; // mix: weights of the float64 spectrum written
+    double out_scale;          // update: multiplier of the written rows
     FftDesc fft;
     int nthr;
     int accumulate;            // 1: u += correction (u already holds the previous iterate)
@@ -178,8 +182,10 @@ struct LineHold {
     static constexpr int value = EPT > RMAX ? EPT : RMAX;
 };
 
-// u0 = inverse float32 DFT of s0 (per row), then the float64 forward DFT of u0
-// (no sin^2 scaling, weight 1/n) -> su.  LDS per row: N float64 complex values.
+// u0 = mid_scale * (inverse float32 DFT of the weighted s0) per row, then the
+// float64 forward DFT of u0 with weights out_w -> su.  Forward solve: weights
+// 1, mid_scale 1, out_w 1/n.  Adjoint: in_w (1/2, 1), mid_scale 1/n, out_w
+// (2, 1) (the transposes of the real DFT pair).  LDS per row: N float64 complex.
 template <int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -192,7 +198,8 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     // float32 view: row r uses the first N float32 complex slots of its float64 line
     Cx<float>* fl = reinterpret_cast<Cx<float>*>(lines);
-    c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
+    c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid,
+                                   a.in_w_end);
     __syncthreads();
     Cx<float>* fbuf = fl + (size_t)line * 2 * N;
     fft_lds<float, true, EPT, RMAX>(fbuf, a.fft, a.ptw32, t, a.nthr, active);
@@ -208,15 +215,16 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
 #pragma unroll
     for (int e = 0; e < H; ++e) {
         const int i = t + e * a.nthr;
-        if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x, (double)hold[e].y};
+        if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x * a.mid_scale, (double)hold[e].y * a.mid_scale};
     }
     __syncthreads();
     fft_lds<double, false, EPT, RMAX>(dbuf, a.fft, a.ptw64, t, a.nthr, active);
-    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.inv_n, a.inv_n);
+    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.out_w_mid, a.out_w_end);
 }
 
-// u = u0 + d (or u += d) with u0, d the float32 inverse DFTs of s0 and sd,
-// summed in float64.  Optionally accumulates per-block sums of d^2 and u^2.
+// u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
+// weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].
+// Optionally accumulates per-block sums of (s d)^2 and u^2.
 template <int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -229,8 +237,9 @@ __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     const size_t stride = 2 * (size_t)N;
-    if (!a.accumulate) c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
-    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.m, jb, 1.0f, 1.0f);
+    if (!a.accumulate)
+        c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid, a.in_w_end);
+    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid, a.in_w_end);
     __syncthreads();
     Cx<float>* b0 = fl + (size_t)line * stride;
     Cx<float>* b1 = b0 + N;
@@ -238,15 +247,17 @@ __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
     fft_lds<float, true, EPT, RMAX>(b1, a.fft, a.ptw32, t, a.nthr, active);
     double sd2 = 0.0, su2 = 0.0;
     if (active) {
+        const double sc = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
         double2* dst = reinterpret_cast<double2*>(a.u + (size_t)j * a.n);
         for (int i = t; i < N; i += a.nthr) {
             const Cx<float> d = b1[i];
+            const double dx = (double)d.x * sc, dy = (double)d.y * sc;
             double2 base;
             if (a.accumulate) base = dst[i];
-            else base = double2{(double)b0[i].x, (double)b0[i].y};
-            const double2 v = double2{base.x + (double)d.x, base.y + (double)d.y};
+            else base = double2{(double)b0[i].x * sc, (double)b0[i].y * sc};
+            const double2 v = double2{base.x + dx, base.y + dy};
             dst[i] = v;
-            sd2 += (double)d.x * d.x + (double)d.y * d.y;
+            sd2 += dx * dx + dy * dy;
             su2 += v.x * v.x + v.y * v.y;
         }
     }
@@ -781,7 +792,12 @@ struct ThetaMixArgs {
     int k64;                   // wavenumbers below this are eliminated in float64
 };
 
-template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID>
+// TRANS = true runs the same refinement for the transposed systems (the
+// adjoint): no coefficient scaling around the solve (the transpose of
+// "analysis with scaling" is the plain synthesis), transposed bands, and for
+// k = 0 the transposed bordered system (the constraint row feeds the even
+// class through -w a_0 and the q = 0 output is zero).
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
 __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Cx<double> red[16];
@@ -817,10 +833,11 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
         const int qq = q == 0 ? 0 : m - q;
         const Cx<double> A = bufd[q], B = bufd[qq];
         const Cx<double> Eq = a.eq64[q];
-        const Cx<double> yq = (cmul(Eq, A) + cmulc(B, Eq)) * (0.5 * (q == 0 ? invm : 2.0 * invm));
+        const double s0 = TRANS ? 0.5 : 0.5 * (q == 0 ? invm : 2.0 * invm);
+        const Cx<double> yq = (cmul(Eq, A) + cmulc(B, Eq)) * s0;
         if (qq != q) {
             const Cx<double> Eqq = a.eq64[qq];
-            bufd[qq] = (cmul(Eqq, B) + cmulc(A, Eqq)) * invm;
+            bufd[qq] = (cmul(Eqq, B) + cmulc(A, Eqq)) * (TRANS ? 0.5 : invm);
         }
         bufd[q] = yq;
     }
@@ -829,6 +846,7 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
     // right-hand side in position order, held in registers across the barrier
     Cx<double> rh[kThetaHold];
     double r0 = a.c0;
+    Cx<double> x0_pin{0.0, 0.0};
     const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
     if (!RESID) {
 #pragma unroll
@@ -841,6 +859,9 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
         }
     } else {
         Cx<double> part{0.0, 0.0};
+        // k = 0, transposed: the even class starts at q = 2 (no coupling to q = 0),
+        // and its right-hand side is B_q - w_q B_0 with w_q = 1/(1 - q^2)
+        const Cx<double> b0 = (TRANS && k == 0) ? a.sa[idx(0)] : Cx<double>{0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < kThetaHold; ++e) {
             const int p = tid + e * nthr;
@@ -850,20 +871,26 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
                     rh[e] = Cx<double>{0.0, 0.0};
                     continue;
                 }
+                const int lo_q = (TRANS && k == 0 && (q & 1) == 0) ? 2 : qlo;
                 double sub, diag, sup;
-                band<double>(q, k, q - 2 < qlo, q + 2 > qhi, false, sub, diag, sup);
+                band<double>(q, k, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
                 Cx<double> ax = bufd[p] * diag;
-                if (q - 2 >= qlo) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
+                if (q - 2 >= lo_q) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
                 if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
-                rh[e] = a.sa[idx(p)] - ax;
-                if (k == 0 && (q & 1) == 0) part = part + bufd[p] * (1.0 / (1.0 - (double)q * (double)q));
+                Cx<double> rhs = a.sa[idx(p)];
+                if (TRANS && k == 0 && (q & 1) == 0) rhs = rhs - b0 * (1.0 / (1.0 - (double)q * (double)q));
+                rh[e] = rhs - ax;
+                if (!TRANS && k == 0 && (q & 1) == 0) part = part + bufd[p] * (1.0 / (1.0 - (double)q * (double)q));
             }
         }
-        if (k == 0) {
+        if (!TRANS && k == 0) {
             const Cx<double> dot = block_sum(part, red);
             const Cx<double> x0 = bufd[0];
             r0 = a.c0 - (x0.x + dot.x);   // the imaginary part of the k = 0 column is zero
         }
+        // transposed, k = 0: the q = 0 entry of the solution is pinned to zero, so the
+        // correction there is minus the q = 0 coefficient of the current iterate
+        if (TRANS && k == 0) x0_pin = bufd[0];
     }
     __syncthreads();
     const bool dbl = k < a.k64;   // ill-conditioned low wavenumbers (and k = 0) in float64
@@ -876,9 +903,11 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
         }
     }
     __syncthreads();
-    if (k == 0) solve_k0<double, SMAXD>(bufd, smem_raw, m, false, r0, a.k0tab, red, tid);
-    else if (dbl) solve_partitioned<double, SMAXD>(bufd, smem_raw, m, k, sine, false, tid);
-    else solve_partitioned<float, SMAXF>(buff, smem_raw, m, k, sine, false, tid);
+    if (k == 0) solve_k0<double, SMAXD>(bufd, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
+    else if (dbl) solve_partitioned<double, SMAXD>(bufd, smem_raw, m, k, sine, TRANS, tid);
+    else solve_partitioned<float, SMAXF>(buff, smem_raw, m, k, sine, TRANS, tid);
+    __syncthreads();
+    if (TRANS && RESID && k == 0 && tid == 0) bufd[0] = Cx<double>{-x0_pin.x, -x0_pin.y};
     __syncthreads();
     if (dbl) {
 #pragma unroll
@@ -898,8 +927,8 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
     const float fm = (float)m;
     for (int q = tid; q <= m / 2; q += nthr) {
         const int qq = q == 0 ? 0 : m - q;
-        const Cx<float> yq = buff[q] * (q == 0 ? fm : fm * 0.5f);
-        const Cx<float> yqq = buff[qq] * (fm * 0.5f);
+        const Cx<float> yq = buff[q] * (TRANS ? 1.0f : (q == 0 ? fm : fm * 0.5f));
+        const Cx<float> yqq = buff[qq] * (TRANS ? 1.0f : fm * 0.5f);
         if (q == 0) {
             buff[0] = yq;
         } else {

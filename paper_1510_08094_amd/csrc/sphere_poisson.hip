@@ -163,14 +163,18 @@ KernelSet<T> pick_kernels(int rmax) {
 struct MixedSet {
     void (*theta_first)(sp::ThetaMixArgs);
     void (*theta_resid)(sp::ThetaMixArgs);
+    void (*theta_first_t)(sp::ThetaMixArgs);   // transposed systems (adjoint)
+    void (*theta_resid_t)(sp::ThetaMixArgs);
     void (*mix)(sp::MixLambdaArgs);
     void (*update)(sp::MixLambdaArgs);
 };
 
 template <int RMAX>
 MixedSet mixed_set() {
-    return MixedSet{&sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false>,
-                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true>,
+    return MixedSet{&sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, false>,
+                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, false>,
+                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, true>,
+                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, true>,
                     &sp::k_lambda_mix<kEPT, RMAX>, &sp::k_lambda_update<kEPT, RMAX>};
 }
 
@@ -408,7 +412,8 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     p->km = pick_mixed(p->rmax);
     set_lds_attr(p->kd, p->lam_lds, p->theta_lds64);
     set_lds_attr(p->kf, p->lam_lds, p->theta_lds64);
-    for (const void* fn : {(const void*)p->km.theta_first, (const void*)p->km.theta_resid})
+    for (const void* fn : {(const void*)p->km.theta_first, (const void*)p->km.theta_resid,
+                           (const void*)p->km.theta_first_t, (const void*)p->km.theta_resid_t})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
@@ -683,7 +688,7 @@ int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status, int iters) 
 
 // MIXED: float64 right-hand side transform, float32 bulk solve, `max_refine`
 // float64-residual corrections (see the mixed kernels).
-int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
+int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hipStream_t s) {
     const int n = p->n, m = p->m, N = p->N;
     const int rw = 1 << p->rw_log2;
     const int nblk = (m + rw - 1) / rw;
@@ -692,9 +697,13 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     const dim3 th_grid(8 * p->k8), th_block(p->theta_threads);
     // 1. float64 lambda transform of sin^2 f -> spec64
     sp::LambdaArgs<double> la{};
-    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n; la.rowscale = p->sin2;
+    // forward: sin^2 f with weight 1/n; adjoint: the transpose of the inverse real DFT
+    // (weights 2 for 0 < k < n/2, 1 at the ends, no sin^2)
+    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n;
+    la.rowscale = adjoint ? nullptr : p->sin2;
     la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.fft = p->fft_lam; la.nthr = p->lam_threads;
-    la.w_mid = 1.0 / n; la.w_end = 1.0 / n;
+    la.w_mid = adjoint ? 2.0 : 1.0 / n;
+    la.w_end = adjoint ? 1.0 : 1.0 / n;
     {
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
         hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
@@ -709,14 +718,16 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     ta.k64 = p->desc.low_k_fp64 < 0 ? std::max(16, m / 64) : std::max(1, p->desc.low_k_fp64);
     {
         ProfScope ps(p, SP_KERNEL_THETA, s);
-        hipLaunchKernelGGL(p->km.theta_first, th_grid, th_block, p->theta_lds64, s, ta);
+        hipLaunchKernelGGL(adjoint ? p->km.theta_first_t : p->km.theta_first, th_grid, th_block, p->theta_lds64,
+                           s, ta);
     }
     const int R = p->desc.max_refine;
     if (R == 0) {
         sp::LambdaArgs<float> lf{};
-        lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.ptw = p->t32.pass_n; lf.rowscale = nullptr;
+        lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.ptw = p->t32.pass_n;
+        lf.rowscale = adjoint ? p->sin2 : nullptr;
         lf.n = n; lf.m = m; lf.N = N; lf.rw_log2 = p->rw_log2; lf.fft = p->fft_lam; lf.nthr = p->lam_threads;
-        lf.w_mid = 1.0f; lf.w_end = 1.0f; lf.out_scale = 1.0;
+        lf.w_mid = adjoint ? 0.5f : 1.0f; lf.w_end = 1.0f; lf.out_scale = adjoint ? 1.0 / n : 1.0;
         ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
         hipLaunchKernelGGL(p->kf.inv, lam_grid, lam_block, p->lam_lds, s, lf);
     } else {
@@ -724,8 +735,19 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
         ma.s0 = p->spec0; ma.sd = p->specd; ma.su = p->specB; ma.u = u;
         ma.tw32 = p->t32.tw_n; ma.tw64 = p->t64.tw_n; ma.partial = want ? p->partial : nullptr;
         ma.ptw32 = p->t32.pass_n; ma.ptw64 = p->t64.pass_n;
-        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2; ma.inv_n = 1.0 / n;
+        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2;
         ma.fft = p->fft_lam; ma.nthr = p->lam_threads; ma.accumulate = 0;
+        if (!adjoint) {
+            ma.in_w_mid = 1.0f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0;
+            ma.out_w_mid = 1.0 / n; ma.out_w_end = 1.0 / n;
+            ma.rowscale = nullptr; ma.out_scale = 1.0;
+        } else {
+            // h = (1/n) C2R(y / c) is the transposed real DFT; its coefficients for the
+            // residual are c n R2C(h), i.e. the raw DFT with weights (1, 2, ..., 2, 1)
+            ma.in_w_mid = 0.5f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0 / n;
+            ma.out_w_mid = 2.0; ma.out_w_end = 1.0;
+            ma.rowscale = p->sin2; ma.out_scale = 1.0 / n;
+        }
         {
             ProfScope ps(p, SP_KERNEL_LAMBDA_MIX, s);
             hipLaunchKernelGGL(p->km.mix, lam_grid, lam_block, p->lam_lds, s, ma);
@@ -735,13 +757,15 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
         for (int it = 1; it <= R; ++it) {
             if (it > 1) {
                 // float64 lambda transform of the current iterate (no sin^2) -> specB
+                if (adjoint) return SP_ERR_INVALID_ARG;   // checked by the caller: adjoint uses one correction
                 la.x = u; la.spec = p->specB; la.rowscale = nullptr;
                 ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
                 hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
             }
             {
                 ProfScope ps(p, SP_KERNEL_THETA_RESID, s);
-                hipLaunchKernelGGL(p->km.theta_resid, th_grid, th_block, p->theta_lds64, s, ta);
+                hipLaunchKernelGGL(adjoint ? p->km.theta_resid_t : p->km.theta_resid, th_grid, th_block,
+                                   p->theta_lds64, s, ta);
             }
             ma.accumulate = it > 1 ? 1 : 0;
             {
@@ -760,6 +784,17 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, hipStream_t s) {
     return SP_OK;
 }
 
+// The adjoint refinement recovers the coefficients of its iterate h through
+// c n R2C(h) (h itself, not sin^2 h, is refined), so any number of corrections
+// would need the sin^2-free iterate kept separately; one correction is used.
+int run_mixed_adjoint(sp_plan p, const double* g, double* fbar, int R, hipStream_t s) {
+    const int saved = p->desc.max_refine;
+    p->desc.max_refine = R;
+    int st = run_mixed(p, g, fbar, 0.0, true, s);
+    p->desc.max_refine = saved;
+    return st;
+}
+
 }  // namespace
 
 extern "C" int sphere_poisson_solve(sp_plan p, const double* f, double* u, double integral,
@@ -771,7 +806,7 @@ extern "C" int sphere_poisson_solve(sp_plan p, const double* f, double* u, doubl
     hipStream_t s = (hipStream_t)hip_stream;
     const double PI = 3.14159265358979323846;
     if (p->desc.precision == SP_MIXED) {
-        int st = run_mixed(p, f, u, integral / (4.0 * PI), s);
+        int st = run_mixed(p, f, u, integral / (4.0 * PI), false, s);
         if (st != SP_OK) return st;
         return finish_info(p, s, info, SP_OK, p->desc.max_refine);
     }
@@ -787,6 +822,12 @@ extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* 
     const size_t bytes = (size_t)p->n * p->m * sizeof(double);
     if (overlap(g, fbar, bytes)) return SP_ERR_ALIAS;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (p->desc.precision == SP_MIXED) {
+        const int R = std::min(p->desc.max_refine, 1);
+        int st = run_mixed_adjoint(p, g, fbar, R, s);
+        if (st != SP_OK) return st;
+        return finish_info(p, s, info, SP_OK, R);
+    }
     int st = run_fp64(p, g, fbar, sp::kSolveTransposed, 0.0, false, true, false, s);
     if (st != SP_OK) return st;
     return finish_info(p, s, info, SP_OK, 0);
