@@ -106,14 +106,15 @@ __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, co
     }
 }
 
+// Each kernel is a __device__ body taking its tile index (a block of rows, or
+// one wavenumber) and its LDS; the __global__ wrappers map blockIdx to the
+// tile, the batch kernels take tiles from a work list.
 template <typename T, int EPT, int RMAX>
-__global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void lambda_fwd_body(const LambdaArgs<T>& a, int jb, unsigned char* smem_raw) {
     Cx<T>* lines = reinterpret_cast<Cx<T>*>(smem_raw);
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
-    const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     Cx<T>* buf = lines + (size_t)line * N;
@@ -131,13 +132,17 @@ __global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
 }
 
 template <typename T, int EPT, int RMAX>
-__global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
+__global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    lambda_fwd_body<T, EPT, RMAX>(a, blockIdx.x, smem_raw);
+}
+
+template <typename T, int EPT, int RMAX>
+__device__ __forceinline__ void lambda_inv_body(const LambdaArgs<T>& a, int jb, unsigned char* smem_raw) {
     Cx<T>* lines = reinterpret_cast<Cx<T>*>(smem_raw);
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
-    const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
@@ -152,6 +157,12 @@ __global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
             dst[i] = double2{(double)z.x * s, (double)z.y * s};
         }
     }
+}
+
+template <typename T, int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    lambda_inv_body<T, EPT, RMAX>(a, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------- mixed lambda passes
@@ -187,13 +198,11 @@ struct LineHold {
 // 1, mid_scale 1, out_w 1/n.  Adjoint: in_w (1/2, 1), mid_scale 1/n, out_w
 // (2, 1) (the transposes of the real DFT pair).  LDS per row: N float64 complex.
 template <int EPT, int RMAX>
-__global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw) {
     Cx<double>* lines = reinterpret_cast<Cx<double>*>(smem_raw);
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
-    const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     // float32 view: row r uses the first N float32 complex slots of its float64 line
@@ -222,18 +231,22 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.out_w_mid, a.out_w_end);
 }
 
+template <int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    lambda_mix_body<EPT, RMAX>(a, blockIdx.x, smem_raw);
+}
+
 // u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
 // weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].
 // Optionally accumulates per-block sums of (s d)^2 and u^2.
 template <int EPT, int RMAX>
-__global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[2][16];
+__device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw,
+                                                   double (*red)[16]) {
     Cx<float>* fl = reinterpret_cast<Cx<float>*>(smem_raw);   // row r: [u0 line | d line]
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
-    const int jb = blockIdx.x;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     const size_t stride = 2 * (size_t)N;
@@ -272,10 +285,18 @@ __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
         if (threadIdx.x == 0) {
             double x = 0.0, y = 0.0;
             for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { x += red[0][w]; y += red[1][w]; }
-            a.partial[2 * blockIdx.x] = x;
-            a.partial[2 * blockIdx.x + 1] = y;
+            a.partial[2 * jb] = x;
+            a.partial[2 * jb + 1] = y;
         }
+        __syncthreads();
     }
+}
+
+template <int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2][16];
+    lambda_update_body<EPT, RMAX>(a, blockIdx.x, smem_raw, red);
 }
 
 // Sum of the per-block partials (one block): out[0] = sum of d^2, out[1] = sum of u^2.
@@ -681,12 +702,9 @@ __device__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char* __restrict__ sc
 }
 
 template <typename T, int EPT, int RMAX, int SMAX>
-__global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ Cx<double> red[16];
+__device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigned char* smem_raw,
+                                           Cx<double>* red) {
     Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
-    const int k = (blockIdx.x & 7) * a.k8 + (blockIdx.x >> 3);
-    if (k > a.N) return;
     const int m = a.m, N = a.N, rwl = a.rw_log2, rw = 1 << rwl;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
@@ -758,6 +776,21 @@ __global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
     }
 }
 
+// Wavenumbers to workgroups, XCD-aware: consecutive workgroup ids go round-robin
+// over the 8 XCDs, so slice x of the k range is given to XCD x.
+__device__ __forceinline__ int theta_k_of_block(int k8) {
+    return (blockIdx.x & 7) * k8 + (blockIdx.x >> 3);
+}
+
+template <typename T, int EPT, int RMAX, int SMAX>
+__global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Cx<double> red[16];
+    const int k = theta_k_of_block(a.k8);
+    if (k > a.N) return;
+    theta_body<T, EPT, RMAX, SMAX>(a, k, smem_raw, red);
+}
+
 // ---------------------------------------------------------------- mixed theta pass
 // Float32 bulk solve with float64 right-hand side / residual (iterative
 // refinement).  Wavenumbers k < k64 (always including k = 0) are eliminated in
@@ -798,13 +831,10 @@ struct ThetaMixArgs {
 // k = 0 the transposed bordered system (the constraint row feeds the even
 // class through -w a_0 and the q = 0 output is zero).
 template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
-__global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ Cx<double> red[16];
+__device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, unsigned char* smem_raw,
+                                                 Cx<double>* red) {
     Cx<double>* bufd = reinterpret_cast<Cx<double>*>(smem_raw);
     Cx<float>* buff = reinterpret_cast<Cx<float>*>(smem_raw);
-    const int k = (blockIdx.x & 7) * a.k8 + (blockIdx.x >> 3);
-    if (k > a.N) return;
     const int m = a.m, N = a.N, rwl = a.rw_log2, rw = 1 << rwl;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
@@ -944,6 +974,15 @@ __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
         if (sine && (j & 1)) x = Cx<float>{-x.x, -x.y};
         a.out[idx(j)] = x;
     }
+}
+
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+__global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Cx<double> red[16];
+    const int k = theta_k_of_block(a.k8);
+    if (k > a.N) return;
+    theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS>(a, k, smem_raw, red);
 }
 
 }  // namespace sp

@@ -10,12 +10,14 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <map>
+#include <memory>
 #include <set>
 #include <string>
 #include <vector>
 
 #include "../../include/sphere_poisson.h"
-#include "sp_kernels.hpp"
+#include "sp_batch.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
@@ -351,6 +353,54 @@ void set_lds_attr(const KernelSet<T>& ks, size_t lam, size_t theta) {
 
 }  // namespace
 
+
+namespace {
+// Theta tables of one m: e^{-i pi q/(2m)}, sin^2(theta_j), the k = 0 LU factors
+// (extended precision) and the quadrature weights of the integral of f.
+void host_theta_tables(int m, std::vector<Cx<double>>& eq, std::vector<double>& sin2, std::vector<double>& k0,
+                       std::vector<double>& fint) {
+    eq.resize(m);
+    for (int t = 0; t < m; ++t) cis_neg(t, 4LL * m, &eq[t].x, &eq[t].y);
+    const long double PI = 3.141592653589793238462643383279502884L;
+    sin2.resize(m);
+    fint.resize(m);
+    for (int j = 0; j < m; ++j) {
+        long double th = ((long double)j + 0.5L) * PI / (long double)m;
+        long double s = sinl(th);
+        sin2[j] = (double)(s * s);
+        // Fejer-type weight: int_0^pi g sin = sum_j W_j g_j for g in span{cos q theta, q < m};
+        // the k = 0 column holds sin^2 f, so the integral of f uses W_j / sin^2(theta_j), times 2 pi.
+        long double W = 0.0L;
+        for (int q = 0; q < m; q += 2) {
+            long double cq = (q == 0 ? 1.0L : 2.0L) / (long double)m;
+            W += cq * cosl((long double)q * th) * 2.0L / (1.0L - (long double)q * q);
+        }
+        fint[j] = (double)(2.0L * PI * W / (s * s));
+    }
+    k0.clear();
+    ClassCounts c = classes(m, false, true);
+    auto lu = [&](int q0, int nc) {
+        std::vector<double> inv(nc), cpd(nc);
+        long double cprev = 0.0L;
+        for (int i = 0; i < nc; ++i) {
+            long double q = q0 + 2.0L * i;
+            long double sub = i == 0 ? 0.0L : (q - 2.0L) * (q - 1.0L) / 4.0L;
+            long double diag = -q * q / 2.0L;
+            long double sup = i == nc - 1 ? 0.0L : (q + 2.0L) * (q + 1.0L) / 4.0L;
+            long double den = diag - sub * cprev;
+            inv[i] = (double)(1.0L / den);
+            long double cp = sup / den;
+            cpd[i] = (double)cp;
+            cprev = cp;
+        }
+        k0.insert(k0.end(), inv.begin(), inv.end());
+        k0.insert(k0.end(), cpd.begin(), cpd.end());
+    };
+    lu(2, c.ncA);
+    lu(1, c.ncB);
+}
+}  // namespace
+
 extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
     if (validate_desc(d) != SP_OK) return 0;
     std::vector<int> rl;
@@ -452,55 +502,16 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     }
 
     // ---- host tables
-    std::vector<Cx<double>> twn(n), eq(m);
+    std::vector<Cx<double>> twn(n), eq;
     for (int t = 0; t < n; ++t) cis_neg(t, n, &twn[t].x, &twn[t].y);
-    for (int t = 0; t < m; ++t) cis_neg(t, 4LL * m, &eq[t].x, &eq[t].y);
+    std::vector<double> sin2, fint, k0;
+    host_theta_tables(m, eq, sin2, k0, fint);
     auto to32 = [](const std::vector<Cx<double>>& v) {
         std::vector<Cx<float>> o(v.size());
         for (size_t i = 0; i < v.size(); ++i) o[i] = Cx<float>{(float)v[i].x, (float)v[i].y};
         return o;
     };
     std::vector<Cx<float>> twn32 = to32(twn), eq32 = to32(eq), pn32 = to32(ptab_n), pm32 = to32(ptab_m);
-    const long double PI = 3.141592653589793238462643383279502884L;
-    std::vector<double> sin2(m), fint(m);
-    for (int j = 0; j < m; ++j) {
-        long double th = ((long double)j + 0.5L) * PI / (long double)m;
-        long double s = sinl(th);
-        sin2[j] = (double)(s * s);
-        // Fejer-type weight: int_0^pi g sin = sum_j W_j g_j for g in span{cos q theta, q < m};
-        // the k = 0 column holds sin^2 f, so the integral of f uses W_j / sin^2(theta_j), times 2 pi.
-        long double W = 0.0L;
-        for (int q = 0; q < m; q += 2) {
-            long double cq = (q == 0 ? 1.0L : 2.0L) / (long double)m;
-            W += cq * cosl((long double)q * th) * 2.0L / (1.0L - (long double)q * q);
-        }
-        fint[j] = (double)(2.0L * PI * W / (s * s));
-    }
-    // k = 0 LU factors of the two cosine classes (even q >= 2, odd q), extended precision
-    std::vector<double> k0;
-    {
-        ClassCounts c = classes(m, false, true);
-        auto lu = [&](int q0, int nc) {
-            std::vector<long double> cp(nc);
-            std::vector<double> inv(nc), cpd(nc);
-            long double cprev = 0.0L;
-            for (int i = 0; i < nc; ++i) {
-                long double q = q0 + 2.0L * i;
-                long double sub = i == 0 ? 0.0L : (q - 2.0L) * (q - 1.0L) / 4.0L;
-                long double diag = -q * q / 2.0L;
-                long double sup = i == nc - 1 ? 0.0L : (q + 2.0L) * (q + 1.0L) / 4.0L;
-                long double den = diag - sub * cprev;
-                inv[i] = (double)(1.0L / den);
-                cp[i] = sup / den;
-                cpd[i] = (double)cp[i];
-                cprev = cp[i];
-            }
-            k0.insert(k0.end(), inv.begin(), inv.end());
-            k0.insert(k0.end(), cpd.begin(), cpd.end());
-        };
-        lu(2, c.ncA);
-        lu(1, c.ncB);
-    }
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
     };
@@ -841,11 +852,345 @@ extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, do
     return run_fp64(p, f, out, sp::kTransformOnly, 0.0, true, false, false, (hipStream_t)hip_stream);
 }
 
+// ------------------------------------------------------------ batches
+namespace {
+
+constexpr int kBatchThreads = 256;
+constexpr size_t kBatchLamLds = 64 * 1024;   // LDS budget of a lambda tile (rows per tile follow)
+
+struct SizeTables {              // tables shared by every problem with the same n (or m)
+    int len = 0;
+    std::vector<int> radices;
+    FftDesc desc{};
+    size_t off64 = 0, off32 = 0, offp64 = 0, offp32 = 0;   // lambda: tw_n and pass tables
+    size_t offeq64 = 0, offeq32 = 0, offsin2 = 0, offk0 = 0, offfint = 0;  // theta extras
+};
+
+struct BatchPlan {
+    int count = 0, precision = 0, device = 0;
+    std::vector<int> n, m;
+    std::vector<const double*> f;
+    std::vector<double*> u;
+    void* block = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double* scal = nullptr;      // [count][4]
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (block) (void)hipFree(block);
+    }
+};
+
+std::mutex g_batch_mu;
+BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebuilt when it changes)
+
+struct BatchKernels {
+    void (*st[sp::kBStages])(const sp::RhsDesc*, const int2*, int, int*);
+};
+
+BatchKernels batch_kernels() {
+    BatchKernels k;
+    k.st[sp::kBLamFwd] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamFwd>;
+    k.st[sp::kBTheta64] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBTheta64>;
+    k.st[sp::kBLamInv] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamInv>;
+    k.st[sp::kBThetaFirst] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBThetaFirst>;
+    k.st[sp::kBLamMix] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamMix>;
+    k.st[sp::kBThetaResid] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBThetaResid>;
+    k.st[sp::kBLamUpd] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamUpd>;
+    return k;
+}
+
+// per-problem launch parameters inside the fixed 256-thread batch tiles
+bool batch_schedule(int n, int m, int* rwl, int* lam_nthr, int* th_fft) {
+    std::vector<int> rl, rt;
+    if (!factorize(n / 2, rl) || !factorize(m, rt)) return false;
+    const int N = n / 2;
+    const int t = fft_threads(rl, N);
+    if (t > kBatchThreads) return false;
+    int best = 0;
+    for (int l = 0; l <= 5; ++l) {
+        const int rw = 1 << l;
+        if (rw * t > kBatchThreads || (size_t)rw * N * sizeof(Cx<double>) > kBatchLamLds) break;
+        best = l;
+        if (rw >= m) break;
+    }
+    *rwl = best;
+    *lam_nthr = t;
+    *th_fft = fft_threads(rt, m);
+    const int need = std::max(std::max(*th_fft, ceil_div(m, sp::kThetaHold)),
+                              std::max(solve_threads(m, kSmaxD), solve_threads(m, kSmaxF)));
+    return need <= kBatchThreads;
+}
+
+}  // namespace
+
+namespace {
+
+void host_theta_tables(int m, std::vector<Cx<double>>& eq, std::vector<double>& sin2, std::vector<double>& k0,
+                       std::vector<double>& fint);
+
+int build_batch(int count, const int* n, const int* m, const double* const* f, double* const* u, int precision,
+                BatchPlan** out) {
+    int dev = 0;
+    size_t lds_limit = 0;
+    int st = query_device(&dev, &lds_limit);
+    if (st != SP_OK) return st;
+    hipDeviceProp_t prop;
+    SP_HIP(hipGetDeviceProperties(&prop, dev));
+    const bool mixed = precision == SP_MIXED;
+    std::vector<int> rwl(count), lnt(count), tft(count);
+    for (int r = 0; r < count; ++r)
+        if (!batch_schedule(n[r], m[r], &rwl[r], &lnt[r], &tft[r])) return SP_ERR_UNSUPPORTED_SIZE;
+
+    BatchPlan* bp = new (std::nothrow) BatchPlan();
+    if (!bp) return SP_ERR_OOM;
+    bp->count = count;
+    bp->precision = precision;
+    bp->device = dev;
+    bp->n.assign(n, n + count);
+    bp->m.assign(m, m + count);
+    bp->f.assign(f, f + count);
+    bp->u.assign(u, u + count);
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
+    // tables per distinct n and m
+    std::map<int, SizeTables> lam, th;
+    std::map<int, std::vector<Cx<double>>> lam_tw, lam_pass, th_pass, th_eq;
+    std::map<int, std::vector<double>> th_sin2, th_k0, th_fint;
+    for (int r = 0; r < count; ++r) {
+        if (!lam.count(n[r])) {
+            SizeTables& t = lam[n[r]];
+            t.len = n[r] / 2;
+            factorize(t.len, t.radices);
+            t.desc = make_desc(t.radices, t.len, &lam_pass[n[r]]);
+            std::vector<Cx<double>>& tw = lam_tw[n[r]];
+            tw.resize(n[r]);
+            for (int i = 0; i < n[r]; ++i) cis_neg(i, n[r], &tw[i].x, &tw[i].y);
+            t.off64 = take(n[r] * sizeof(Cx<double>));
+            t.off32 = take(n[r] * sizeof(Cx<float>));
+            t.offp64 = take(lam_pass[n[r]].size() * sizeof(Cx<double>));
+            t.offp32 = take(lam_pass[n[r]].size() * sizeof(Cx<float>));
+        }
+        if (!th.count(m[r])) {
+            SizeTables& t = th[m[r]];
+            t.len = m[r];
+            factorize(t.len, t.radices);
+            t.desc = make_desc(t.radices, t.len, &th_pass[m[r]]);
+            host_theta_tables(m[r], th_eq[m[r]], th_sin2[m[r]], th_k0[m[r]], th_fint[m[r]]);
+            t.offp64 = take(th_pass[m[r]].size() * sizeof(Cx<double>));
+            t.offp32 = take(th_pass[m[r]].size() * sizeof(Cx<float>));
+            t.offeq64 = take(m[r] * sizeof(Cx<double>));
+            t.offeq32 = take(m[r] * sizeof(Cx<float>));
+            t.offsin2 = take(m[r] * sizeof(double));
+            t.offk0 = take(th_k0[m[r]].size() * sizeof(double));
+            t.offfint = take(m[r] * sizeof(double));
+        }
+    }
+    // per-problem workspace
+    std::vector<size_t> o64(count), oB(count), o0(count), od(count), opart(count);
+    std::vector<int> nblk(count);
+    size_t lam_lds = 0, th_lds = 0;
+    for (int r = 0; r < count; ++r) {
+        const int rw = 1 << rwl[r];
+        nblk[r] = (m[r] + rw - 1) / rw;
+        const size_t elems = (size_t)nblk[r] * (n[r] / 2 + 1) * rw;
+        o64[r] = take(elems * sizeof(Cx<double>));
+        if (mixed) {
+            oB[r] = take(elems * sizeof(Cx<double>));
+            o0[r] = take(elems * sizeof(Cx<float>));
+            od[r] = take(elems * sizeof(Cx<float>));
+            opart[r] = take(2 * (size_t)nblk[r] * sizeof(double));
+        }
+        lam_lds = std::max(lam_lds, (size_t)rw * (n[r] / 2) * sizeof(Cx<double>));
+        th_lds = std::max(th_lds, theta_lds_bytes<double>(m[r], std::max(solve_threads(m[r], kSmaxD),
+                                                                            solve_threads(m[r], kSmaxF))));
+    }
+    // work lists: (rhs, tile) sorted by decreasing tile cost
+    std::vector<int2> lam_items, th_items;
+    for (int r = 0; r < count; ++r) {
+        for (int jb = 0; jb < nblk[r]; ++jb) lam_items.push_back(make_int2(r, jb));
+        for (int k = 0; k <= n[r] / 2; ++k) th_items.push_back(make_int2(r, k));
+    }
+    std::stable_sort(lam_items.begin(), lam_items.end(), [&](int2 x, int2 y) {
+        return (long long)n[x.x] << rwl[x.x] > (long long)n[y.x] << rwl[y.x];
+    });
+    std::stable_sort(th_items.begin(), th_items.end(), [&](int2 x, int2 y) { return m[x.x] > m[y.x]; });
+    const size_t o_desc = take(count * sizeof(sp::RhsDesc));
+    const size_t o_lam_items = take(lam_items.size() * sizeof(int2));
+    const size_t o_th_items = take(th_items.size() * sizeof(int2));
+    const size_t o_ctr = take(sp::kBStages * sizeof(int));
+    const size_t o_scal = take(4 * (size_t)count * sizeof(double));
+    const size_t o_nblk = take(count * sizeof(int));
+
+    hipError_t e = hipMalloc(&bp->block, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete bp;
+        return SP_ERR_OOM;
+    }
+    unsigned char* B = (unsigned char*)bp->block;
+    bp->scal = (double*)(B + o_scal);
+    std::vector<sp::RhsDesc> descs(count);
+    for (int r = 0; r < count; ++r) {
+        const SizeTables& L = lam[n[r]];
+        const SizeTables& T = th[m[r]];
+        sp::RhsDesc& d = descs[r];
+        d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r];
+        d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r];
+        d.k64 = std::max(16, m[r] / 64);
+        d.c0 = 0.0;
+        d.fl = L.desc; d.ft = T.desc;
+        d.f = f[r]; d.u = u[r];
+        d.spec64 = (Cx<double>*)(B + o64[r]);
+        d.specB = mixed ? (Cx<double>*)(B + oB[r]) : nullptr;
+        d.spec0 = mixed ? (Cx<float>*)(B + o0[r]) : nullptr;
+        d.specd = mixed ? (Cx<float>*)(B + od[r]) : nullptr;
+        d.partial = mixed ? (double*)(B + opart[r]) : nullptr;
+        d.tw64n = (const Cx<double>*)(B + L.off64);
+        d.tw32n = (const Cx<float>*)(B + L.off32);
+        d.p64n = (const Cx<double>*)(B + L.offp64);
+        d.p32n = (const Cx<float>*)(B + L.offp32);
+        d.p64m = (const Cx<double>*)(B + T.offp64);
+        d.p32m = (const Cx<float>*)(B + T.offp32);
+        d.eq64 = (const Cx<double>*)(B + T.offeq64);
+        d.eq32 = (const Cx<float>*)(B + T.offeq32);
+        d.sin2 = (const double*)(B + T.offsin2);
+        d.k0tab = (const double*)(B + T.offk0);
+        d.fint_w = (const double*)(B + T.offfint);
+        d.scal = bp->scal + 4 * r;
+    }
+    auto to32 = [](const std::vector<Cx<double>>& v) {
+        std::vector<Cx<float>> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = Cx<float>{(float)v[i].x, (float)v[i].y};
+        return o;
+    };
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> uploads;
+    auto stage = [&](size_t o, const void* src, size_t bytes) {
+        std::vector<unsigned char> v((const unsigned char*)src, (const unsigned char*)src + bytes);
+        uploads.emplace_back(o, std::move(v));
+    };
+    for (auto& kv : lam) {
+        const int nn = kv.first;
+        auto t32 = to32(lam_tw[nn]);
+        auto p32 = to32(lam_pass[nn]);
+        stage(kv.second.off64, lam_tw[nn].data(), lam_tw[nn].size() * sizeof(Cx<double>));
+        stage(kv.second.off32, t32.data(), t32.size() * sizeof(Cx<float>));
+        stage(kv.second.offp64, lam_pass[nn].data(), lam_pass[nn].size() * sizeof(Cx<double>));
+        stage(kv.second.offp32, p32.data(), p32.size() * sizeof(Cx<float>));
+    }
+    for (auto& kv : th) {
+        const int mm = kv.first;
+        auto p32 = to32(th_pass[mm]);
+        auto e32 = to32(th_eq[mm]);
+        stage(kv.second.offp64, th_pass[mm].data(), th_pass[mm].size() * sizeof(Cx<double>));
+        stage(kv.second.offp32, p32.data(), p32.size() * sizeof(Cx<float>));
+        stage(kv.second.offeq64, th_eq[mm].data(), th_eq[mm].size() * sizeof(Cx<double>));
+        stage(kv.second.offeq32, e32.data(), e32.size() * sizeof(Cx<float>));
+        stage(kv.second.offsin2, th_sin2[mm].data(), th_sin2[mm].size() * sizeof(double));
+        stage(kv.second.offk0, th_k0[mm].data(), th_k0[mm].size() * sizeof(double));
+        stage(kv.second.offfint, th_fint[mm].data(), th_fint[mm].size() * sizeof(double));
+    }
+    stage(o_desc, descs.data(), descs.size() * sizeof(sp::RhsDesc));
+    stage(o_lam_items, lam_items.data(), lam_items.size() * sizeof(int2));
+    stage(o_th_items, th_items.data(), th_items.size() * sizeof(int2));
+    stage(o_nblk, nblk.data(), nblk.size() * sizeof(int));
+    for (auto& up : uploads) {
+        e = hipMemcpy(B + up.first, up.second.data(), up.second.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { delete bp; return hip_fail(e, "batch upload"); }
+    }
+
+    // graph: counter reset, the stage kernels, per-problem norms
+    BatchKernels K = batch_kernels();
+    std::vector<int> stages = mixed ? std::vector<int>{sp::kBLamFwd, sp::kBThetaFirst, sp::kBLamMix,
+                                                       sp::kBThetaResid, sp::kBLamUpd}
+                                    : std::vector<int>{sp::kBLamFwd, sp::kBTheta64, sp::kBLamInv};
+    e = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamCreate"); }
+    std::vector<int> grids(sp::kBStages, 0);
+    std::vector<size_t> ldss(sp::kBStages, 0);
+    for (int stg : stages) {
+        const bool is_theta = stg == sp::kBTheta64 || stg == sp::kBThetaFirst || stg == sp::kBThetaResid;
+        const size_t lds = is_theta ? th_lds : lam_lds;
+        if (lds + 1024 > lds_limit) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
+        (void)hipFuncSetAttribute((const void*)K.st[stg], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)K.st[stg], kBatchThreads, lds) !=
+                hipSuccess || occ < 1)
+            occ = 1;
+        const int nit = is_theta ? (int)th_items.size() : (int)lam_items.size();
+        grids[stg] = std::max(1, std::min(nit, prop.multiProcessorCount * occ));
+        ldss[stg] = lds;
+    }
+    (void)hipGetLastError();
+    e = hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamBeginCapture"); }
+    int* ctr = (int*)(B + o_ctr);
+    const sp::RhsDesc* dd = (const sp::RhsDesc*)(B + o_desc);
+    hipLaunchKernelGGL(sp::k_batch_reset, dim3(1), dim3(64), 0, bp->cap, ctr, (int)sp::kBStages);
+    for (int stg : stages) {
+        const bool is_theta = stg == sp::kBTheta64 || stg == sp::kBThetaFirst || stg == sp::kBThetaResid;
+        const int2* items = (const int2*)(B + (is_theta ? o_th_items : o_lam_items));
+        const int nit = is_theta ? (int)th_items.size() : (int)lam_items.size();
+        hipLaunchKernelGGL(K.st[stg], dim3(grids[stg]), dim3(kBatchThreads), ldss[stg], bp->cap, dd, items, nit,
+                           ctr + stg);
+    }
+    if (mixed) hipLaunchKernelGGL(sp::k_batch_norms, dim3(count), dim3(256), 0, bp->cap, dd, (const int*)(B + o_nblk));
+    e = hipStreamEndCapture(bp->cap, &bp->graph);
+    if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamEndCapture"); }
+    e = hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { delete bp; return hip_fail(e, "hipGraphInstantiate"); }
+    *out = bp;
+    return SP_OK;
+}
+
+bool batch_matches(const BatchPlan* bp, int count, const int* n, const int* m, const double* const* f,
+                   double* const* u, int precision, int dev) {
+    if (!bp || bp->count != count || bp->precision != precision || bp->device != dev) return false;
+    for (int r = 0; r < count; ++r)
+        if (bp->n[r] != n[r] || bp->m[r] != m[r] || bp->f[r] != f[r] || bp->u[r] != u[r]) return false;
+    return true;
+}
+
+}  // namespace
+
 extern "C" int sphere_poisson_solve_batch(int count, const int* n, const int* m, const double* const* f,
                                           double* const* u, int precision, void* hip_stream, sp_info* infos) {
-    (void)precision; (void)hip_stream; (void)infos;
     if (count <= 0 || !n || !m || !f || !u) return SP_ERR_INVALID_ARG;
-    return SP_ERR_UNSUPPORTED_SIZE;
+    if (precision != SP_FP64 && precision != SP_MIXED) return SP_ERR_INVALID_ARG;
+    for (int r = 0; r < count; ++r) {
+        if (!f[r] || !u[r] || n[r] < 4 || (n[r] & 1) || m[r] < 4) return SP_ERR_INVALID_ARG;
+        if (overlap(f[r], u[r], (size_t)n[r] * m[r] * sizeof(double))) return SP_ERR_ALIAS;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    int dev = 0;
+    SP_HIP(hipGetDevice(&dev));
+    if (!batch_matches(g_batch, count, n, m, f, u, precision, dev)) {
+        delete g_batch;
+        g_batch = nullptr;
+        BatchPlan* bp = nullptr;
+        int st = build_batch(count, n, m, f, u, precision, &bp);
+        if (st != SP_OK) return st;
+        g_batch = bp;
+    }
+    SP_HIP(hipGraphLaunch(g_batch->exec, s));
+    if (infos) {
+        SP_HIP(hipStreamSynchronize(s));
+        std::vector<double> sc(4 * (size_t)count);
+        SP_HIP(hipMemcpy(sc.data(), g_batch->scal, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int r = 0; r < count; ++r) {
+            infos[r].iters = precision == SP_MIXED ? 1 : 0;
+            infos[r].rel_correction = (precision == SP_MIXED && sc[4 * r + 2] > 0.0)
+                                          ? std::sqrt(sc[4 * r + 1] / sc[4 * r + 2]) : 0.0;
+            infos[r].f_integral = sc[4 * r];
+            infos[r].status = SP_OK;
+        }
+    }
+    return SP_OK;
 }
 
 extern "C" const char* sphere_poisson_strerror(int code) {
