@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -177,8 +178,39 @@ def main():
                                "host_cpus": os.cpu_count()}
         if u is not None:
             out["rel_err_vs_oracle"] = float(np.linalg.norm(u - u_or) / np.linalg.norm(u_or))
-    print(json.dumps(out), flush=True)
     plan.close()
+    del fg, ug
+    if not args.no_batch:
+        out["batch"] = bench_batch(args, P, S, torch, np)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, P, S, torch, np):
+    """512 right-hand sides, n, m i.i.d. uniform on {128, 192, ..., 2048}, band
+    limit floor(min(n, m)/4), mixed precision, one graph launch per step."""
+    sizes = S.batch_sizes(3, 512, [64 * j for j in range(2, 33)])
+    log("bench: synthesising the 512-problem batch")
+    t0 = time.time()
+    fs = [torch.from_numpy(S.sphere_field(3, r, int(n), int(m), int(min(n, m)) // 4)).cuda()
+          for r, (n, m) in enumerate(sizes)]
+    us = [torch.empty_like(f) for f in fs]
+    log("bench: batch inputs ready in %.1fs" % (time.time() - t0))
+    dof = int(sum(int(n) * int(m) for n, m in sizes))
+    for _ in range(max(1, args.warmup)):
+        P.solve_batch(fs, "mixed", outs=us)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(1, args.steps // 4)
+    e0.record(stream)
+    for _ in range(steps):
+        P.solve_batch(fs, "mixed", outs=us)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log("bench: batch %.3f ms/step, %.3e DOF/s" % (ms, dof / (ms * 1e-3)))
+    return {"workload": "batch_512_rhs_n_m_uniform_128_2048_mixed", "rhs": 512, "dof": dof,
+            "ms_per_step": ms, "dof_per_s": dof / (ms * 1e-3), "launches_per_step": 1}
 
 
 if __name__ == "__main__":

@@ -69,6 +69,7 @@ typedef enum {
 
 /* flags */
 #define SP_SYNC_INFO 0x1u   /* the solve synchronises `hip_stream` and fills *info (norms computed on device) */
+#define SP_AUTOTUNE 0x2u    /* plan: time candidate radix orders and row tiles for this size (cached, see below) */
 
 typedef struct {
     int n_lambda;       /* n: samples in lambda (even, >= 4) */
@@ -76,7 +77,7 @@ typedef struct {
     int precision;      /* sp_precision */
     int max_refine;     /* MIXED: number of iterative-refinement corrections (>= 0; 1 is enough for 1e-10) */
     double tol;         /* MIXED with SP_SYNC_INFO: required ||last correction|| / ||u|| (<= 0: no check) */
-    unsigned flags;     /* SP_SYNC_INFO */
+    unsigned flags;     /* SP_SYNC_INFO | SP_AUTOTUNE */
     int low_k_fp64;     /* MIXED: wavenumbers k < low_k_fp64 are eliminated in float64 (their systems
                            have condition numbers near (m/k)^2, too large for float32 corrections);
                            < 0: automatic, max(16, m/64); 0 or 1: only k = 0 */
@@ -96,6 +97,13 @@ typedef struct sp_plan_s* sp_plan;
  * (exact-angle reduction) and uploads them, allocates the spectrum workspace
  * (about 8 bytes per grid point for SP_FP64, 24 for SP_MIXED) and picks the
  * launch schedule.  `hip_stream` is used for the uploads.
+ * Schedules: the radix order of the lambda and theta transforms and the rows
+ * per lambda tile come from the autotuner cache when it has an entry for the
+ * size (text file named by SPHERE_POISSON_TUNE_CACHE, default
+ * $HOME/.cache/sphere_poisson_tune.txt), else from a fixed rule.  With
+ * SP_AUTOTUNE in desc->flags (or SPHERE_POISSON_AUTOTUNE=1 in the environment)
+ * missing entries are measured first: every candidate is timed with HIP events
+ * on a scratch problem of the same transform length, and the fastest is kept.
  * Errors: SP_ERR_INVALID_ARG, SP_ERR_UNSUPPORTED_SIZE, SP_ERR_OOM, SP_ERR_HIP,
  * SP_ERR_NO_DEVICE.  On error *out is set to NULL. */
 int sphere_poisson_plan(sp_plan* out, const sp_desc* desc, void* hip_stream);

@@ -16,7 +16,7 @@ import re
 import torch  # loads the HIP runtime that the library then shares
 
 __all__ = ["SpherePoisson", "SpherePoissonFunction", "solve_batch", "library", "LibraryMissing",
-           "SP_FP64", "SP_MIXED", "SP_SYNC_INFO", "SpError", "exported_symbols"]
+           "SP_FP64", "SP_MIXED", "SP_SYNC_INFO", "SP_AUTOTUNE", "SpError", "exported_symbols"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsphere_poisson.so")
@@ -24,6 +24,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sphere_poisson.h")
 
 SP_FP64, SP_MIXED = 0, 1
 SP_SYNC_INFO = 0x1
+SP_AUTOTUNE = 0x2
 _STATUS = {0: "SP_OK", 1: "SP_ERR_INVALID_ARG", 2: "SP_ERR_UNSUPPORTED_SIZE", 3: "SP_ERR_OOM",
            4: "SP_ERR_HIP", 5: "SP_ERR_NOT_CONVERGED", 6: "SP_ERR_ALIAS", 7: "SP_ERR_NO_DEVICE",
            8: "SP_ERR_BAD_PLAN"}
@@ -116,14 +117,15 @@ class SpherePoisson:
     """A plan for one grid size and precision (owns the device workspace)."""
 
     def __init__(self, n: int, m: int, precision: str = "fp64", max_refine: int = 1, tol: float = 0.0,
-                 sync_info: bool = False, device=None, low_k_fp64: int = -1):
+                 sync_info: bool = False, device=None, low_k_fp64: int = -1, autotune: bool = False):
         lib = library()
         self.n, self.m = int(n), int(m)
         self.precision = {"fp64": SP_FP64, "mixed": SP_MIXED}[precision]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.desc = SpDesc(self.n, self.m, self.precision, int(max_refine), float(tol),
-                           SP_SYNC_INFO if sync_info else 0, int(low_k_fp64))
+                           (SP_SYNC_INFO if sync_info else 0) | (SP_AUTOTUNE if autotune else 0),
+                           int(low_k_fp64))
         self._plan = ctypes.c_void_p()
         self.info = SpInfo()
         with torch.cuda.device(self.device):

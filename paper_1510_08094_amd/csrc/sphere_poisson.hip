@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <functional>
+#include <sys/stat.h>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -255,7 +258,7 @@ int validate_desc(const sp_desc* d) {
     if (!d) return SP_ERR_INVALID_ARG;
     if (d->n_lambda < 4 || (d->n_lambda & 1) || d->m_theta < 4) return SP_ERR_INVALID_ARG;
     if (d->precision != SP_FP64 && d->precision != SP_MIXED) return SP_ERR_INVALID_ARG;
-    if (d->max_refine < 0 || (d->flags & ~SP_SYNC_INFO)) return SP_ERR_INVALID_ARG;
+    if (d->max_refine < 0 || (d->flags & ~(SP_SYNC_INFO | SP_AUTOTUNE))) return SP_ERR_INVALID_ARG;
     if (d->n_lambda > (1 << 20) || d->m_theta > (1 << 20)) return SP_ERR_UNSUPPORTED_SIZE;
     std::vector<int> r;
     if (!factorize(d->n_lambda / 2, r) || !factorize(d->m_theta, r)) return SP_ERR_UNSUPPORTED_SIZE;
@@ -411,16 +414,20 @@ extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
     return layout_for(d->n_lambda, d->m_theta, 1 << rwl, d->precision == SP_MIXED).total;
 }
 
-extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_stream) {
-    if (!out) return SP_ERR_INVALID_ARG;
+namespace {
+// A launch schedule: radix order of both transforms and rows per lambda tile
+// (rw_log2 < 0: the fixed rule).
+struct Sched {
+    std::vector<int> lam, theta;
+    int rw_log2 = -1;
+};
+
+int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* out) {
     *out = nullptr;
-    int st = validate_desc(d);
-    if (st != SP_OK) return st;
     int dev = 0;
     size_t lds_limit = 0;
-    st = query_device(&dev, &lds_limit);
+    int st = query_device(&dev, &lds_limit);
     if (st != SP_OK) return st;
-    hipStream_t stream = (hipStream_t)hip_stream;
 
     sp_plan p = new (std::nothrow) sp_plan_s();
     if (!p) return SP_ERR_OOM;
@@ -431,9 +438,9 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     p->N = p->n / 2;
     const int n = p->n, m = p->m, N = p->N;
 
-    std::vector<int> rl, rt;
-    factorize(N, rl);
-    factorize(m, rt);
+    std::vector<int> rl = sc.lam, rt = sc.theta;
+    if (rl.empty()) factorize(N, rl);
+    if (rt.empty()) factorize(m, rt);
     p->rmax = 1;
     for (int r : rl) p->rmax = std::max(p->rmax, r);
     for (int r : rt) p->rmax = std::max(p->rmax, r);
@@ -444,6 +451,11 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     if (!lambda_schedule(N, m, rl, lds_limit, &p->rw_log2, &p->lam_threads, &p->lam_lds)) {
         delete p;
         return SP_ERR_UNSUPPORTED_SIZE;
+    }
+    if (sc.rw_log2 >= 0 && sc.rw_log2 <= 5 && (1 << sc.rw_log2) * p->lam_threads <= 1024 &&
+        ((size_t)N << sc.rw_log2) * sizeof(Cx<double>) <= lds_limit) {
+        p->rw_log2 = sc.rw_log2;
+        p->lam_lds = ((size_t)N << sc.rw_log2) * sizeof(Cx<double>);
     }
     p->theta_fft_threads = fft_threads(rt, m);
     int ptotD = solve_threads(m, kSmaxD), ptotF = solve_threads(m, kSmaxF);
@@ -537,6 +549,276 @@ extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_str
     plan_register(p);
     *out = p;
     return SP_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// Per transform length: the lambda transform of n (radix order and rows per
+// tile, any precision) and the theta transform of m (radix order, per
+// precision).  Candidates are timed with HIP events on scratch problems; the
+// fastest schedules are kept in a text cache, one line per entry:
+//   <arch> lam <n> <rw_log2> <r1,r2,...>      <arch> theta <m> <precision> <r1,r2,...>
+std::mutex g_tune_mu;
+std::map<std::string, std::string> g_tune;   // key -> value, loaded lazily
+bool g_tune_loaded = false;
+
+std::string tune_path() {
+    const char* e = std::getenv("SPHERE_POISSON_TUNE_CACHE");
+    if (e && *e) return e;
+    const char* h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/sphere_poisson_tune.txt";
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    FILE* fp = std::fopen(tune_path().c_str(), "r");
+    if (!fp) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), fp)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        size_t cut = l.rfind(' ');
+        if (cut == std::string::npos) continue;
+        g_tune[l.substr(0, cut)] = l.substr(cut + 1);
+    }
+    std::fclose(fp);
+}
+
+void tune_save_locked() {
+    std::string path = tune_path();
+    size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        (void)::mkdir(dir.c_str(), 0755);
+    }
+    std::string tmp = path + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    for (auto& kv : g_tune) std::fprintf(fp, "%s %s\n", kv.first.c_str(), kv.second.c_str());
+    std::fclose(fp);
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string radix_str(const std::vector<int>& r) {
+    std::string s;
+    for (size_t i = 0; i < r.size(); ++i) s += (i ? "," : "") + std::to_string(r[i]);
+    return s;
+}
+
+std::vector<int> parse_radices(const std::string& s) {
+    std::vector<int> r;
+    size_t i = 0;
+    while (i < s.size()) {
+        size_t j = s.find(',', i);
+        if (j == std::string::npos) j = s.size();
+        r.push_back(std::atoi(s.substr(i, j - i).c_str()));
+        i = j + 1;
+    }
+    return r;
+}
+
+std::string key_lam(int n) { return "gfx950 lam " + std::to_string(n); }
+std::string key_theta(int m, int prec) { return "gfx950 theta " + std::to_string(m) + " " + std::to_string(prec); }
+
+bool valid_radices(const std::vector<int>& r, int L) {
+    long long prod = 1;
+    for (int x : r) {
+        static const int ok[] = {2, 3, 4, 5, 7, 8, 11, 13, 16, 17, 19, 23, 29, 31};
+        if (std::find(std::begin(ok), std::end(ok), x) == std::end(ok)) return false;
+        prod *= x;
+    }
+    return prod == L && (int)r.size() <= sp::kMaxPass;
+}
+
+// Radix orders to try for length L: power-of-two groupings (2, 4, 8, 16) with
+// at most one pass more than the fewest, each combined with the odd primes in
+// a few orders.
+std::vector<std::vector<int>> radix_candidates(int L) {
+    std::vector<std::vector<int>> out;
+    int e = 0, odd = L;
+    while (odd % 2 == 0) { odd /= 2; ++e; }
+    std::vector<int> primes;
+    for (int p : {3, 5, 7, 11, 13, 17, 19, 23, 29, 31})
+        while (odd % p == 0) { primes.push_back(p); odd /= p; }
+    if (odd != 1) return out;
+    std::vector<std::vector<int>> groups;
+    int minp = 1 << 30;
+    for (int c16 = 0; 4 * c16 <= e; ++c16)
+        for (int c8 = 0; 4 * c16 + 3 * c8 <= e; ++c8)
+            for (int c4 = 0; 4 * c16 + 3 * c8 + 2 * c4 <= e; ++c4) {
+                int c2 = e - 4 * c16 - 3 * c8 - 2 * c4;
+                if (c2 > 1) continue;
+                minp = std::min(minp, c16 + c8 + c4 + c2);
+            }
+    for (int c16 = 0; 4 * c16 <= e; ++c16)
+        for (int c8 = 0; 4 * c16 + 3 * c8 <= e; ++c8)
+            for (int c4 = 0; 4 * c16 + 3 * c8 + 2 * c4 <= e; ++c4) {
+                int c2 = e - 4 * c16 - 3 * c8 - 2 * c4;
+                if (c2 > 1 || c16 + c8 + c4 + c2 > minp + 1) continue;
+                std::vector<int> g;
+                g.insert(g.end(), c16, 16);
+                g.insert(g.end(), c8, 8);
+                g.insert(g.end(), c4, 4);
+                g.insert(g.end(), c2, 2);
+                groups.push_back(g);
+            }
+    for (auto& g : groups) {
+        std::vector<int> pa = g, pb;
+        pa.insert(pa.end(), primes.begin(), primes.end());        // powers of two first
+        pb = primes;
+        pb.insert(pb.end(), g.begin(), g.end());                  // odd primes first
+        std::vector<int> pc(pa.rbegin(), pa.rend());             // reversed
+        for (auto* v : {&pa, &pb, &pc})
+            if (std::find(out.begin(), out.end(), *v) == out.end()) out.push_back(*v);
+    }
+    if (out.size() > 24) out.resize(24);
+    return out;
+}
+
+float time_ms(hipStream_t s, const std::function<void()>& fn, int reps) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    fn();   // warm-up
+    (void)hipEventRecord(a, s);
+    for (int i = 0; i < reps; ++i) fn();
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool fwd_sin2,
+             bool adjoint_weights, bool want_fint, hipStream_t s);
+int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hipStream_t s);
+
+// Time one schedule: a full solve of a scratch problem (n, m, precision).
+float time_schedule(const sp_desc& base, const Sched& sc, hipStream_t s, double* x, double* y) {
+    sp_plan p = nullptr;
+    if (plan_create(&base, s, sc, &p) != SP_OK || !p) {
+        (void)hipGetLastError();
+        return 1e30f;
+    }
+    auto fn = [&]() {
+        if (base.precision == SP_MIXED) (void)run_mixed(p, x, y, 0.0, false, s);
+        else (void)run_fp64(p, x, y, sp::kSolve, 0.0, true, false, false, s);
+    };
+    float ms = time_ms(s, fn, 3);
+    if (hipGetLastError() != hipSuccess) ms = 1e30f;
+    plan_unregister(p);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p->block);
+    delete p;
+    return ms;
+}
+
+// Fill missing cache entries for (n, m, precision) by measurement.
+int autotune(const sp_desc* d, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    const int n = d->n_lambda, m = d->m_theta, prec = d->precision;
+    const bool need_lam = !g_tune.count(key_lam(n)), need_th = !g_tune.count(key_theta(m, prec));
+    if (!need_lam && !need_th) return SP_OK;
+    // scratch problems: n x 256 rows for the lambda transform, 512 x m for the theta transform
+    const int mt = 256, nt = 512;
+    const size_t cells = std::max((size_t)n * mt, (size_t)nt * m);
+    double* x = nullptr;
+    double* y = nullptr;
+    if (hipMalloc(&x, cells * sizeof(double)) != hipSuccess || hipMalloc(&y, cells * sizeof(double)) != hipSuccess) {
+        (void)hipFree(x);
+        (void)hipGetLastError();
+        return SP_ERR_OOM;
+    }
+    (void)hipMemsetAsync(x, 0, cells * sizeof(double), s);
+    if (need_lam) {
+        sp_desc b = *d;
+        b.m_theta = mt;
+        b.precision = SP_FP64;
+        b.flags = 0;
+        Sched best;
+        float best_ms = 1e30f;
+        for (auto& r : radix_candidates(n / 2)) {
+            for (int rwl = 0; rwl <= 5; ++rwl) {
+                Sched sc;
+                sc.lam = r;
+                sc.rw_log2 = rwl;
+                const float ms = time_schedule(b, sc, s, x, y);
+                if (ms < best_ms) { best_ms = ms; best = sc; }
+            }
+        }
+        if (best_ms < 1e29f)
+            g_tune[key_lam(n)] = std::to_string(best.rw_log2) + ":" + radix_str(best.lam);
+    }
+    if (need_th) {
+        sp_desc b = *d;
+        b.n_lambda = nt;
+        b.flags = 0;
+        Sched best;
+        float best_ms = 1e30f;
+        for (auto& r : radix_candidates(m)) {
+            Sched sc;
+            sc.theta = r;
+            const float ms = time_schedule(b, sc, s, x, y);
+            if (ms < best_ms) { best_ms = ms; best = sc; }
+        }
+        if (best_ms < 1e29f) g_tune[key_theta(m, prec)] = radix_str(best.theta);
+    }
+    (void)hipFree(x);
+    (void)hipFree(y);
+    (void)hipGetLastError();
+    tune_save_locked();
+    return SP_OK;
+}
+
+// The schedule the cache holds for (n, m, precision) (empty fields: fixed rule).
+Sched cached_schedule(int n, int m, int prec) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    Sched sc;
+    auto it = g_tune.find(key_lam(n));
+    if (it != g_tune.end()) {
+        size_t c = it->second.find(':');
+        if (c != std::string::npos) {
+            std::vector<int> r = parse_radices(it->second.substr(c + 1));
+            if (valid_radices(r, n / 2)) {
+                sc.lam = r;
+                sc.rw_log2 = std::atoi(it->second.substr(0, c).c_str());
+            }
+        }
+    }
+    it = g_tune.find(key_theta(m, prec));
+    if (it != g_tune.end()) {
+        std::vector<int> r = parse_radices(it->second);
+        if (valid_radices(r, m)) sc.theta = r;
+    }
+    return sc;
+}
+
+bool autotune_requested(const sp_desc* d) {
+    const char* e = std::getenv("SPHERE_POISSON_AUTOTUNE");
+    return (d->flags & SP_AUTOTUNE) || (e && *e == '1');
+}
+
+}  // namespace
+
+extern "C" int sphere_poisson_plan(sp_plan* out, const sp_desc* d, void* hip_stream) {
+    if (!out) return SP_ERR_INVALID_ARG;
+    *out = nullptr;
+    int st = validate_desc(d);
+    if (st != SP_OK) return st;
+    int dev = 0;
+    size_t lds_limit = 0;
+    st = query_device(&dev, &lds_limit);
+    if (st != SP_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (autotune_requested(d)) {
+        st = autotune(d, stream);
+        if (st != SP_OK) return st;
+    }
+    return plan_create(d, stream, cached_schedule(d->n_lambda, d->m_theta, d->precision), out);
 }
 
 namespace {
@@ -903,10 +1185,12 @@ BatchKernels batch_kernels() {
     return k;
 }
 
-// per-problem launch parameters inside the fixed 256-thread batch tiles
-bool batch_schedule(int n, int m, int* rwl, int* lam_nthr, int* th_fft) {
-    std::vector<int> rl, rt;
-    if (!factorize(n / 2, rl) || !factorize(m, rt)) return false;
+// per-problem launch parameters inside the fixed 256-thread batch tiles;
+// rl / rt: radix orders (empty: fixed rule)
+bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, int* rwl, int* lam_nthr,
+                    int* th_fft) {
+    if (rl.empty() && !factorize(n / 2, rl)) return false;
+    if (rt.empty() && !factorize(m, rt)) return false;
     const int N = n / 2;
     const int t = fft_threads(rl, N);
     if (t > kBatchThreads) return false;
@@ -941,9 +1225,33 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     hipDeviceProp_t prop;
     SP_HIP(hipGetDeviceProperties(&prop, dev));
     const bool mixed = precision == SP_MIXED;
+    // radix orders per distinct n and m: the autotuner cache, measured first when requested
+    const char* env = std::getenv("SPHERE_POISSON_AUTOTUNE");
+    if (env && *env == '1') {
+        std::map<int, int> seen_n, seen_m;
+        for (int r = 0; r < count; ++r) {
+            if (seen_n.count(n[r]) && seen_m.count(m[r])) continue;
+            seen_n[n[r]] = 1;
+            seen_m[m[r]] = 1;
+            sp_desc d{};
+            d.n_lambda = n[r]; d.m_theta = m[r]; d.precision = precision; d.max_refine = 1;
+            int st2 = autotune(&d, nullptr);
+            if (st2 != SP_OK) return st2;
+        }
+    }
     std::vector<int> rwl(count), lnt(count), tft(count);
-    for (int r = 0; r < count; ++r)
-        if (!batch_schedule(n[r], m[r], &rwl[r], &lnt[r], &tft[r])) return SP_ERR_UNSUPPORTED_SIZE;
+    std::vector<std::vector<int>> rls(count), rts(count);
+    for (int r = 0; r < count; ++r) {
+        Sched sc = cached_schedule(n[r], m[r], precision);
+        rls[r] = sc.lam;
+        rts[r] = sc.theta;
+        if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r])) {
+            rls[r].clear();
+            rts[r].clear();
+            if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r]))
+                return SP_ERR_UNSUPPORTED_SIZE;
+        }
+    }
 
     BatchPlan* bp = new (std::nothrow) BatchPlan();
     if (!bp) return SP_ERR_OOM;
@@ -958,35 +1266,43 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
     // tables per distinct n and m
-    std::map<int, SizeTables> lam, th;
-    std::map<int, std::vector<Cx<double>>> lam_tw, lam_pass, th_pass, th_eq;
-    std::map<int, std::vector<double>> th_sin2, th_k0, th_fint;
+    // tables per distinct (size, radix order)
+    std::map<std::string, SizeTables> lam, th;
+    std::map<std::string, std::vector<Cx<double>>> lam_tw, lam_pass, th_pass, th_eq;
+    std::map<std::string, std::vector<double>> th_sin2, th_k0, th_fint;
+    std::vector<std::string> lkey(count), tkey(count);
     for (int r = 0; r < count; ++r) {
-        if (!lam.count(n[r])) {
-            SizeTables& t = lam[n[r]];
+        lkey[r] = std::to_string(n[r]) + "|" + radix_str(rls[r]);
+        tkey[r] = std::to_string(m[r]) + "|" + radix_str(rts[r]);
+    }
+    for (int r = 0; r < count; ++r) {
+        const std::string& lk = lkey[r];
+        const std::string& tk = tkey[r];
+        if (!lam.count(lk)) {
+            SizeTables& t = lam[lk];
             t.len = n[r] / 2;
-            factorize(t.len, t.radices);
-            t.desc = make_desc(t.radices, t.len, &lam_pass[n[r]]);
-            std::vector<Cx<double>>& tw = lam_tw[n[r]];
+            t.radices = rls[r];
+            t.desc = make_desc(t.radices, t.len, &lam_pass[lk]);
+            std::vector<Cx<double>>& tw = lam_tw[lk];
             tw.resize(n[r]);
             for (int i = 0; i < n[r]; ++i) cis_neg(i, n[r], &tw[i].x, &tw[i].y);
             t.off64 = take(n[r] * sizeof(Cx<double>));
             t.off32 = take(n[r] * sizeof(Cx<float>));
-            t.offp64 = take(lam_pass[n[r]].size() * sizeof(Cx<double>));
-            t.offp32 = take(lam_pass[n[r]].size() * sizeof(Cx<float>));
+            t.offp64 = take(lam_pass[lk].size() * sizeof(Cx<double>));
+            t.offp32 = take(lam_pass[lk].size() * sizeof(Cx<float>));
         }
-        if (!th.count(m[r])) {
-            SizeTables& t = th[m[r]];
+        if (!th.count(tk)) {
+            SizeTables& t = th[tk];
             t.len = m[r];
-            factorize(t.len, t.radices);
-            t.desc = make_desc(t.radices, t.len, &th_pass[m[r]]);
-            host_theta_tables(m[r], th_eq[m[r]], th_sin2[m[r]], th_k0[m[r]], th_fint[m[r]]);
-            t.offp64 = take(th_pass[m[r]].size() * sizeof(Cx<double>));
-            t.offp32 = take(th_pass[m[r]].size() * sizeof(Cx<float>));
+            t.radices = rts[r];
+            t.desc = make_desc(t.radices, t.len, &th_pass[tk]);
+            host_theta_tables(m[r], th_eq[tk], th_sin2[tk], th_k0[tk], th_fint[tk]);
+            t.offp64 = take(th_pass[tk].size() * sizeof(Cx<double>));
+            t.offp32 = take(th_pass[tk].size() * sizeof(Cx<float>));
             t.offeq64 = take(m[r] * sizeof(Cx<double>));
             t.offeq32 = take(m[r] * sizeof(Cx<float>));
             t.offsin2 = take(m[r] * sizeof(double));
-            t.offk0 = take(th_k0[m[r]].size() * sizeof(double));
+            t.offk0 = take(th_k0[tk].size() * sizeof(double));
             t.offfint = take(m[r] * sizeof(double));
         }
     }
@@ -1036,8 +1352,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     bp->scal = (double*)(B + o_scal);
     std::vector<sp::RhsDesc> descs(count);
     for (int r = 0; r < count; ++r) {
-        const SizeTables& L = lam[n[r]];
-        const SizeTables& T = th[m[r]];
+        const SizeTables& L = lam[lkey[r]];
+        const SizeTables& T = th[tkey[r]];
         sp::RhsDesc& d = descs[r];
         d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r];
         d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r];
@@ -1074,7 +1390,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         uploads.emplace_back(o, std::move(v));
     };
     for (auto& kv : lam) {
-        const int nn = kv.first;
+        const std::string& nn = kv.first;
         auto t32 = to32(lam_tw[nn]);
         auto p32 = to32(lam_pass[nn]);
         stage(kv.second.off64, lam_tw[nn].data(), lam_tw[nn].size() * sizeof(Cx<double>));
@@ -1083,7 +1399,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         stage(kv.second.offp32, p32.data(), p32.size() * sizeof(Cx<float>));
     }
     for (auto& kv : th) {
-        const int mm = kv.first;
+        const std::string& mm = kv.first;
         auto p32 = to32(th_pass[mm]);
         auto e32 = to32(th_eq[mm]);
         stage(kv.second.offp64, th_pass[mm].data(), th_pass[mm].size() * sizeof(Cx<double>));
