@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain 800 MB device-to-device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -73,6 +75,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(args, torch)
+        return
 
     import paper_1510_08094_amd as P
     import sh_inputs as S
@@ -183,6 +189,27 @@ def main():
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(args, torch):
+    """A plain copy of 10^8 float64 values (800 MB read, 800 MB written): the
+    kernel against which FETCH_SIZE / WRITE_SIZE counts are scaled."""
+    dev = torch.device("cuda", 0)
+    x = torch.ones(10 ** 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nbytes = 2 * x.numel() * 8
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "read_bytes": nbytes // 2, "write_bytes": nbytes // 2,
+                      "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def bench_batch(args, P, S, torch, np):

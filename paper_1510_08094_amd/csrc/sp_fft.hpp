@@ -287,13 +287,21 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
 
 // Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
 // radices compiled into this instantiation.
+// The line is base[off .. off + N).
 template <typename T, bool INV, int EPT, int RMAX>
-__device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ buf, const FftDesc& d,
-                                        const Cx<T>* __restrict__ ptw, int t, int nthr, bool active) {
+__device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ base, int off, const FftDesc& d,
+                                        const Cx<T>* __restrict__ ptw, int t0, int nthr, bool active) {
     int Ns = 1;
     for (int p = 0; p < d.npass; ++p) {
         const int R = d.radix[p];
         const Cx<T>* tw = ptw + d.tw_off[p];
+        // The thread index and the line offset are made opaque on every pass:
+        // otherwise the LDS addresses of all radix cases are hoisted out of the
+        // loop and stay live across it, which costs tens of registers and
+        // forces spills.
+        int t = t0, o = off;
+        asm volatile("" : "+v"(t), "+v"(o));
+        Cx<T>* buf = base + o;
         switch (R) {
             case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
             case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;

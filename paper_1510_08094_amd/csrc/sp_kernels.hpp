@@ -127,7 +127,7 @@ __device__ __forceinline__ void lambda_fwd_body(const LambdaArgs<T>& a, int jb, 
         }
     }
     __syncthreads();
-    fft_lds<T, false, EPT, RMAX>(buf, a.fft, a.ptw, t, a.nthr, active);
+    fft_lds<T, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
     r2c_split_store<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
 }
 
@@ -147,7 +147,7 @@ __device__ __forceinline__ void lambda_inv_body(const LambdaArgs<T>& a, int jb, 
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
     __syncthreads();
-    fft_lds<T, true, EPT, RMAX>(lines + (size_t)line * N, a.fft, a.ptw, t, a.nthr, active);
+    fft_lds<T, true, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
     if (active) {
         const Cx<T>* buf = lines + (size_t)line * N;
         const double s = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
@@ -211,7 +211,7 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
                                    a.in_w_end);
     __syncthreads();
     Cx<float>* fbuf = fl + (size_t)line * 2 * N;
-    fft_lds<float, true, EPT, RMAX>(fbuf, a.fft, a.ptw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N, a.fft, a.ptw32, t, a.nthr, active);
     constexpr int H = LineHold<EPT, RMAX>::value;
     Cx<float> hold[H];
 #pragma unroll
@@ -227,7 +227,7 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
         if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x * a.mid_scale, (double)hold[e].y * a.mid_scale};
     }
     __syncthreads();
-    fft_lds<double, false, EPT, RMAX>(dbuf, a.fft, a.ptw64, t, a.nthr, active);
+    fft_lds<double, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw64, t, a.nthr, active);
     r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.out_w_mid, a.out_w_end);
 }
 
@@ -256,8 +256,8 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
     __syncthreads();
     Cx<float>* b0 = fl + (size_t)line * stride;
     Cx<float>* b1 = b0 + N;
-    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(b0, a.fft, a.ptw32, t, a.nthr, active);
-    fft_lds<float, true, EPT, RMAX>(b1, a.fft, a.ptw32, t, a.nthr, active);
+    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N, a.fft, a.ptw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N + N, a.fft, a.ptw32, t, a.nthr, active);
     double sd2 = 0.0, su2 = 0.0;
     if (active) {
         const double sc = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
@@ -383,7 +383,7 @@ __device__ __forceinline__ ClassInfo make_class(int q0, int qhi) {
 // neighbouring separators (spikes v, w), the separators form a tridiagonal
 // system solved by parallel cyclic reduction, and the interiors are rebuilt.
 template <typename T, int SMAX>
-__device__ void solve_partitioned(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch,
+__device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch,
                                   int m, int k, bool sine, bool transposed, int tid) {
     const int qhi = sine ? m : m - 1;
     const ClassInfo A = make_class<SMAX>(sine ? 2 : 0, qhi);
@@ -552,7 +552,7 @@ __device__ __forceinline__ Cx<double> block_sum(Cx<double> v, Cx<double>* red) {
 // a_0 then follows from the constraint (transposed: the constraint row feeds
 // the even class and the q = 0 output is zero).  Always float64.
 template <int SMAX>
-__device__ void scan_affine(Cx<double>& A, double& Bm, unsigned char* scratch, int tid,
+__device__ __forceinline__ void scan_affine(Cx<double>& A, double& Bm, unsigned char* scratch, int tid,
                             int cls_lo, int cls_hi, int ptot, bool reverse, bool valid) {
     // inclusive scan of maps f_p(z) = A_p + B_p z over the chunks of a class
     // (forward: f_p applied after f_{p-1}; reverse: after f_{p+1}).
@@ -580,7 +580,7 @@ __device__ void scan_affine(Cx<double>& A, double& Bm, unsigned char* scratch, i
 }
 
 template <typename T, int SMAX>
-__device__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
+__device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
                          bool transposed, double c0, const double* __restrict__ tab, Cx<double>* red,
                          int tid) {
     const int qhi = m - 1;
@@ -724,7 +724,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
         if (tid == 0) *a.fint_out = s.x;
     }
     __syncthreads();
-    fft_lds<T, false, EPT, RMAX>(buf, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
+    fft_lds<T, false, EPT, RMAX>(buf, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
     const bool scale = a.mode == kSolve;
     for (int q = tid; q <= m / 2; q += nthr) {
         const int qq = q == 0 ? 0 : m - q;
@@ -766,7 +766,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
         }
     }
     __syncthreads();
-    fft_lds<T, true, EPT, RMAX>(buf, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
+    fft_lds<T, true, EPT, RMAX>(buf, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
     for (int j = tid; j < m; j += nthr) {
         const size_t idx = ((((size_t)(j >> rwl)) * (N + 1) + k) << rwl) + (j & (rw - 1));
         const int pos = (j & 1) ? m - ((j + 1) >> 1) : (j >> 1);
@@ -858,7 +858,7 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
         if (tid == 0) *a.fint_out = sm.x;
     }
     __syncthreads();
-    fft_lds<double, false, EPT, RMAX>(bufd, a.fft, a.tw64, tid, a.nthr_fft, tid < a.nthr_fft);
+    fft_lds<double, false, EPT, RMAX>(bufd, 0, a.fft, a.tw64, tid, a.nthr_fft, tid < a.nthr_fft);
     for (int q = tid; q <= m / 2; q += nthr) {
         const int qq = q == 0 ? 0 : m - q;
         const Cx<double> A = bufd[q], B = bufd[qq];
@@ -967,7 +967,7 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
         }
     }
     __syncthreads();
-    fft_lds<float, true, EPT, RMAX>(buff, a.fft, a.tw32, tid, a.nthr_fft, tid < a.nthr_fft);
+    fft_lds<float, true, EPT, RMAX>(buff, 0, a.fft, a.tw32, tid, a.nthr_fft, tid < a.nthr_fft);
     const float finvm = 1.0f / fm;
     for (int j = tid; j < m; j += nthr) {
         Cx<float> x = buff[posj(j)] * finvm;
