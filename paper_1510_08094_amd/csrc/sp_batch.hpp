@@ -20,6 +20,7 @@ struct RhsDesc {
     double* u;
     Cx<double>* spec64;
     Cx<double>* specB;
+    Cx<double>* fco;
     Cx<float>* spec0;
     Cx<float>* specd;
     const Cx<double>* tw64n;
@@ -70,7 +71,7 @@ __device__ __forceinline__ MixLambdaArgs mix_args(const RhsDesc& d) {
 
 __device__ __forceinline__ ThetaMixArgs theta_mix_args(const RhsDesc& d, bool resid) {
     ThetaMixArgs ta{};
-    ta.sa = d.spec64; ta.su = d.specB; ta.out = resid ? d.specd : d.spec0;
+    ta.sa = d.spec64; ta.fco = d.fco; ta.su = d.specB; ta.out = resid ? d.specd : d.spec0;
     ta.tw64 = d.p64m; ta.eq64 = d.eq64; ta.tw32 = d.p32m; ta.eq32 = d.eq32;
     ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.rw_log2 = d.rw_log2;
     ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.k8 = 0;

@@ -382,9 +382,21 @@ __device__ __forceinline__ ClassInfo make_class(int q0, int qhi) {
 // first row is a separator, the interior rows are eliminated against the two
 // neighbouring separators (spikes v, w), the separators form a tridiagonal
 // system solved by parallel cyclic reduction, and the interiors are rebuilt.
-template <typename T, int SMAX>
-__device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch,
-                                  int m, int k, bool sine, bool transposed, int tid) {
+// Right-hand-side slot of row ii of a thread's chunk in the "solve order"
+// used for values kept between kernels: class A rows first, then class B,
+// each interleaved over the chunks (consecutive threads, consecutive slots).
+// A class of nc rows in p chunks of s rows uses s p <= nc + p - 1 slots, so
+// the slots of a line (both classes, chunks of at least 12 rows, at most
+// m/12 + 2 chunks) stay below m + m/8 + 16.
+__host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + (m >> 3) + 16; }
+
+// load(p, q, slot) returns the right-hand side of the row of coefficient q
+// (LDS position p, solve-order slot); store(p, x) receives the solution.
+// Every load happens before the first barrier and every store after the last
+// use of the LDS scratch.
+template <typename T, int SMAX, typename Load, typename Store>
+__device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
+                                                     int m, int k, bool sine, bool transposed, int tid) {
     const int qhi = sine ? m : m - 1;
     const ClassInfo A = make_class<SMAX>(sine ? 2 : 0, qhi);
     const ClassInfo B = make_class<SMAX>(1, qhi);
@@ -402,11 +414,12 @@ __device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsig
     Cx<T> dr[SMAX];
     T vr[SMAX], cr[SMAX];
     // load the chunk (LDS position of coefficient q: q for cosine, m - q for sine)
+    const int slot0 = (inA ? 0 : A.s * A.p) + p;
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            dr[ii] = buf[sine ? m - q : q];
+            dr[ii] = load(sine ? m - q : q, q, slot0 + ii * C.p);
         }
     }
     __syncthreads();   // B1: the column may now be overwritten by scratch
@@ -516,15 +529,23 @@ __device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsig
     if (cnt > 0 && tid + 1 < cls_hi) Sn = de[tid + 1];
     __syncthreads();   // scratch no longer needed: write the solution
     if (cnt > 0) {
-        buf[sine ? m - (C.q0 + 2 * lo) : C.q0 + 2 * lo] = S;
+        store(sine ? m - (C.q0 + 2 * lo) : C.q0 + 2 * lo, S);
 #pragma unroll
         for (int ii = 1; ii < SMAX; ++ii) {
             if (ii <= ni) {
                 const int q = C.q0 + 2 * (lo + ii);
-                buf[sine ? m - q : q] = dr[ii] - S * vr[ii] - Sn * cr[ii];
+                store(sine ? m - q : q, dr[ii] - S * vr[ii] - Sn * cr[ii]);
             }
         }
     }
+}
+
+// In place on a column held in LDS.
+template <typename T, int SMAX>
+__device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch,
+                                                  int m, int k, bool sine, bool transposed, int tid) {
+    solve_partitioned_io<T, SMAX>([&](int p, int, int) { return buf[p]; },
+                                  [&](int p, Cx<T> x) { buf[p] = x; }, scratch, m, k, sine, transposed, tid);
 }
 
 // Block-wide sum of one complex double per thread (result valid in every thread).
@@ -807,7 +828,8 @@ __global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
 constexpr int kThetaHold = 16;   // positions per thread in the residual / conversion loops
 
 struct ThetaMixArgs {
-    Cx<double>* sa;            // float64 spectrum of sin^2 b; replaced by F (position order)
+    const Cx<double>* sa;      // float64 spectrum of sin^2 b (first solve)
+    Cx<double>* fco;           // F per wavenumber, stride solve_slot_stride(m): written by the first solve
     const Cx<double>* su;      // RESID: float64 spectrum of the current iterate
     Cx<float>* out;            // float32 spectrum written (s0 or sd)
     const Cx<double>* tw64;    // per-pass twiddles of the length-m DFT
@@ -824,6 +846,87 @@ struct ThetaMixArgs {
     double* fint_out;
     int k64;                   // wavenumbers below this are eliminated in float64
 };
+
+// k = 0 of the mixed theta pass: the bordered constraint system, always in
+// float64.  F is kept in position order.  RESID: r = F - (L) X with the
+// constraint row r_0 = c0 - (X_0 + sum_{q>=2 even} X_q/(1 - q^2)); TRANS:
+// the transposed bordered system (the constraint row feeds the even class
+// through -w b_0 and the q = 0 entry of the solution is pinned to zero, so the
+// correction there is minus the q = 0 coefficient of the current iterate).
+// On return the float32 column buff holds the solution.
+template <int SMAXD, bool RESID, bool TRANS>
+__device__ __forceinline__ void theta_mixed_k0(const ThetaMixArgs& a, Cx<double>* bufd, Cx<float>* buff,
+                                               Cx<double>* F, unsigned char* smem_raw, Cx<double>* red, int tid) {
+    const int m = a.m, nthr = blockDim.x;
+    Cx<double> rh[kThetaHold];
+    double r0 = a.c0;
+    Cx<double> x0_pin{0.0, 0.0};
+    const int qhi = m - 1;
+    if (!RESID) {
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) {
+                rh[e] = bufd[p];
+                F[p] = rh[e];
+            }
+        }
+    } else {
+        Cx<double> part{0.0, 0.0};
+        // transposed: the even class starts at q = 2 (no coupling to q = 0), and its
+        // right-hand side is B_q - w_q B_0 with w_q = 1/(1 - q^2)
+        const Cx<double> b0 = TRANS ? F[0] : Cx<double>{0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < kThetaHold; ++e) {
+            const int q = tid + e * nthr;
+            if (q < m) {
+                if (q == 0) {
+                    rh[e] = Cx<double>{0.0, 0.0};
+                    continue;
+                }
+                const int lo_q = (TRANS && (q & 1) == 0) ? 2 : 0;
+                double sub, diag, sup;
+                band<double>(q, 0, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
+                Cx<double> ax = bufd[q] * diag;
+                if (q - 2 >= lo_q) ax = ax + bufd[q - 2] * sub;
+                if (q + 2 <= qhi) ax = ax + bufd[q + 2] * sup;
+                Cx<double> rhs = F[q];
+                if (TRANS && (q & 1) == 0) rhs = rhs - b0 * (1.0 / (1.0 - (double)q * (double)q));
+                rh[e] = rhs - ax;
+                if (!TRANS && (q & 1) == 0) part = part + bufd[q] * (1.0 / (1.0 - (double)q * (double)q));
+            }
+        }
+        if (!TRANS) {
+            const Cx<double> dot = block_sum(part, red);
+            const Cx<double> x0 = bufd[0];
+            r0 = a.c0 - (x0.x + dot.x);   // the imaginary part of the k = 0 column is zero
+        }
+        if (TRANS) x0_pin = bufd[0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kThetaHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) bufd[p] = rh[e];
+    }
+    __syncthreads();
+    solve_k0<double, SMAXD>(bufd, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
+    __syncthreads();
+    if (TRANS && RESID && tid == 0) bufd[0] = Cx<double>{-x0_pin.x, -x0_pin.y};
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kThetaHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) rh[e] = bufd[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kThetaHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) buff[p] = Cx<float>{(float)rh[e].x, (float)rh[e].y};
+    }
+    __syncthreads();
+}
 
 // TRANS = true runs the same refinement for the transposed systems (the
 // adjoint): no coefficient scaling around the solve (the transpose of
@@ -873,85 +976,42 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
     }
     __syncthreads();
 
-    // right-hand side in position order, held in registers across the barrier
-    Cx<double> rh[kThetaHold];
-    double r0 = a.c0;
-    Cx<double> x0_pin{0.0, 0.0};
     const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
-    if (!RESID) {
-#pragma unroll
-        for (int e = 0; e < kThetaHold; ++e) {
-            const int p = tid + e * nthr;
-            if (p < m) {
-                rh[e] = bufd[p];
-                a.sa[idx(p)] = rh[e];
+    Cx<double>* Fk = a.fco + (size_t)k * solve_slot_stride(m);
+    if (k != 0) {
+        // The right-hand side of each row is formed as the solve loads it:
+        // first solve, F itself (also kept, in solve order, for the
+        // correction); correction, r = F - (L - k^2) X in float64 from the
+        // analysed iterate X in LDS.  The solution goes straight to the
+        // float32 column used by the synthesis.
+        auto load = [&](int p, int q, int slot) -> Cx<double> {
+            if (!RESID) {
+                const Cx<double> f = bufd[p];
+                Fk[slot] = f;
+                return f;
             }
+            double sub, diag, sup;
+            band<double>(q, k, q - 2 < qlo, q + 2 > qhi, TRANS, sub, diag, sup);
+            Cx<double> ax = bufd[p] * diag;
+            if (q - 2 >= qlo) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
+            if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
+            return Fk[slot] - ax;
+        };
+        if (k < a.k64) {   // ill-conditioned low wavenumbers: float64 elimination
+            solve_partitioned_io<double, SMAXD>(
+                load, [&](int p, Cx<double> x) { buff[p] = Cx<float>{(float)x.x, (float)x.y}; }, smem_raw, m, k,
+                sine, TRANS, tid);
+        } else {
+            solve_partitioned_io<float, SMAXF>(
+                [&](int p, int q, int slot) {
+                    const Cx<double> r = load(p, q, slot);
+                    return Cx<float>{(float)r.x, (float)r.y};
+                },
+                [&](int p, Cx<float> x) { buff[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
         }
+        __syncthreads();
     } else {
-        Cx<double> part{0.0, 0.0};
-        // k = 0, transposed: the even class starts at q = 2 (no coupling to q = 0),
-        // and its right-hand side is B_q - w_q B_0 with w_q = 1/(1 - q^2)
-        const Cx<double> b0 = (TRANS && k == 0) ? a.sa[idx(0)] : Cx<double>{0.0, 0.0};
-#pragma unroll
-        for (int e = 0; e < kThetaHold; ++e) {
-            const int p = tid + e * nthr;
-            if (p < m) {
-                const int q = sine ? m - p : p;
-                if (k == 0 && q == 0) {
-                    rh[e] = Cx<double>{0.0, 0.0};
-                    continue;
-                }
-                const int lo_q = (TRANS && k == 0 && (q & 1) == 0) ? 2 : qlo;
-                double sub, diag, sup;
-                band<double>(q, k, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
-                Cx<double> ax = bufd[p] * diag;
-                if (q - 2 >= lo_q) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
-                if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
-                Cx<double> rhs = a.sa[idx(p)];
-                if (TRANS && k == 0 && (q & 1) == 0) rhs = rhs - b0 * (1.0 / (1.0 - (double)q * (double)q));
-                rh[e] = rhs - ax;
-                if (!TRANS && k == 0 && (q & 1) == 0) part = part + bufd[p] * (1.0 / (1.0 - (double)q * (double)q));
-            }
-        }
-        if (!TRANS && k == 0) {
-            const Cx<double> dot = block_sum(part, red);
-            const Cx<double> x0 = bufd[0];
-            r0 = a.c0 - (x0.x + dot.x);   // the imaginary part of the k = 0 column is zero
-        }
-        // transposed, k = 0: the q = 0 entry of the solution is pinned to zero, so the
-        // correction there is minus the q = 0 coefficient of the current iterate
-        if (TRANS && k == 0) x0_pin = bufd[0];
-    }
-    __syncthreads();
-    const bool dbl = k < a.k64;   // ill-conditioned low wavenumbers (and k = 0) in float64
-#pragma unroll
-    for (int e = 0; e < kThetaHold; ++e) {
-        const int p = tid + e * nthr;
-        if (p < m) {
-            if (dbl) bufd[p] = rh[e];
-            else buff[p] = Cx<float>{(float)rh[e].x, (float)rh[e].y};
-        }
-    }
-    __syncthreads();
-    if (k == 0) solve_k0<double, SMAXD>(bufd, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
-    else if (dbl) solve_partitioned<double, SMAXD>(bufd, smem_raw, m, k, sine, TRANS, tid);
-    else solve_partitioned<float, SMAXF>(buff, smem_raw, m, k, sine, TRANS, tid);
-    __syncthreads();
-    if (TRANS && RESID && k == 0 && tid == 0) bufd[0] = Cx<double>{-x0_pin.x, -x0_pin.y};
-    __syncthreads();
-    if (dbl) {
-#pragma unroll
-        for (int e = 0; e < kThetaHold; ++e) {
-            const int p = tid + e * nthr;
-            if (p < m) rh[e] = bufd[p];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < kThetaHold; ++e) {
-            const int p = tid + e * nthr;
-            if (p < m) buff[p] = Cx<float>{(float)rh[e].x, (float)rh[e].y};
-        }
-        __syncthreads();
+        theta_mixed_k0<SMAXD, RESID, TRANS>(a, bufd, buff, Fk, smem_raw, red, tid);
     }
     // float32 synthesis
     const float fm = (float)m;

@@ -227,6 +227,7 @@ struct sp_plan_s {
     Cx<float>* spec0 = nullptr;    // float32 spectrum of the first iterate
     Cx<float>* specd = nullptr;    // float32 spectrum of the correction
     double* partial = nullptr;     // per lambda block: sum d^2, sum u^2
+    Cx<double>* fco = nullptr;     // theta coefficients F of sin^2 f per wavenumber (solve order)
     // profiling: event pairs around launches
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
@@ -268,7 +269,7 @@ int validate_desc(const sp_desc* d) {
 struct Layout {
     size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32, off_p64n, off_p32n;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
-    size_t off_specB, off_spec0, off_specd, off_partial;
+    size_t off_specB, off_spec0, off_specd, off_partial, off_fco;
     size_t spec_elems;
 };
 
@@ -297,6 +298,7 @@ Layout layout_for(int n, int m, int rw, bool mixed) {
         L.off_spec0 = take(L.spec_elems * sizeof(Cx<float>));
         L.off_specd = take(L.spec_elems * sizeof(Cx<float>));
         L.off_partial = take(2 * nblk * sizeof(double));
+        L.off_fco = take((N + 1) * (size_t)sp::solve_slot_stride(m) * sizeof(Cx<double>));
     }
     L.total = off;
     return L;
@@ -511,6 +513,7 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         p->spec0 = (Cx<float>*)(b + L.off_spec0);
         p->specd = (Cx<float>*)(b + L.off_specd);
         p->partial = (double*)(b + L.off_partial);
+        p->fco = (Cx<double>*)(b + L.off_fco);
     }
 
     // ---- host tables
@@ -1003,7 +1006,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     }
     // 2. first solve
     sp::ThetaMixArgs ta{};
-    ta.sa = p->spec64; ta.su = p->specB; ta.out = p->spec0;
+    ta.sa = p->spec64; ta.fco = p->fco; ta.su = p->specB; ta.out = p->spec0;
     ta.tw64 = p->t64.pass_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.pass_m; ta.eq32 = p->t32.eq;
     ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2; ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
@@ -1307,7 +1310,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         }
     }
     // per-problem workspace
-    std::vector<size_t> o64(count), oB(count), o0(count), od(count), opart(count);
+    std::vector<size_t> o64(count), oB(count), o0(count), od(count), opart(count), ofco(count);
     std::vector<int> nblk(count);
     size_t lam_lds = 0, th_lds = 0;
     for (int r = 0; r < count; ++r) {
@@ -1320,6 +1323,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             o0[r] = take(elems * sizeof(Cx<float>));
             od[r] = take(elems * sizeof(Cx<float>));
             opart[r] = take(2 * (size_t)nblk[r] * sizeof(double));
+            ofco[r] = take((size_t)(n[r] / 2 + 1) * sp::solve_slot_stride(m[r]) * sizeof(Cx<double>));
         }
         lam_lds = std::max(lam_lds, (size_t)rw * (n[r] / 2) * sizeof(Cx<double>));
         th_lds = std::max(th_lds, theta_lds_bytes<double>(m[r], std::max(solve_threads(m[r], kSmaxD),
@@ -1366,6 +1370,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         d.spec0 = mixed ? (Cx<float>*)(B + o0[r]) : nullptr;
         d.specd = mixed ? (Cx<float>*)(B + od[r]) : nullptr;
         d.partial = mixed ? (double*)(B + opart[r]) : nullptr;
+        d.fco = mixed ? (Cx<double>*)(B + ofco[r]) : nullptr;
         d.tw64n = (const Cx<double>*)(B + L.off64);
         d.tw32n = (const Cx<float>*)(B + L.off32);
         d.p64n = (const Cx<double>*)(B + L.offp64);
