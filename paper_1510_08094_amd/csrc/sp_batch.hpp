@@ -12,7 +12,7 @@
 namespace sp {
 
 struct RhsDesc {
-    int n, m, N, rw_log2;
+    int n, m, N, rw_log2, lay_log2;
     int lam_nthr, theta_nthr_fft, k64;
     double c0;
     FftDesc fl, ft;
@@ -51,7 +51,7 @@ enum BatchStage {
 
 __device__ __forceinline__ LambdaArgs<double> lam_args(const RhsDesc& d) {
     LambdaArgs<double> la{};
-    la.n = d.n; la.m = d.m; la.N = d.N; la.rw_log2 = d.rw_log2;
+    la.n = d.n; la.m = d.m; la.N = d.N; la.rw_log2 = d.rw_log2; la.lay_log2 = d.lay_log2;
     la.fft = d.fl; la.nthr = d.lam_nthr;
     la.tw = d.tw64n; la.ptw = d.p64n;
     return la;
@@ -62,7 +62,7 @@ __device__ __forceinline__ MixLambdaArgs mix_args(const RhsDesc& d) {
     ma.s0 = d.spec0; ma.sd = d.specd; ma.su = d.specB; ma.u = d.u;
     ma.tw32 = d.tw32n; ma.tw64 = d.tw64n; ma.ptw32 = d.p32n; ma.ptw64 = d.p64n;
     ma.partial = d.partial; ma.rowscale = nullptr;
-    ma.n = d.n; ma.m = d.m; ma.N = d.N; ma.rw_log2 = d.rw_log2;
+    ma.n = d.n; ma.m = d.m; ma.N = d.N; ma.rw_log2 = d.rw_log2; ma.lay_log2 = d.lay_log2;
     ma.in_w_mid = 1.0f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0;
     ma.out_w_mid = 1.0 / d.n; ma.out_w_end = 1.0 / d.n; ma.out_scale = 1.0;
     ma.fft = d.fl; ma.nthr = d.lam_nthr; ma.accumulate = 0;
@@ -73,7 +73,7 @@ __device__ __forceinline__ ThetaMixArgs theta_mix_args(const RhsDesc& d, bool re
     ThetaMixArgs ta{};
     ta.sa = d.spec64; ta.fco = d.fco; ta.su = d.specB; ta.out = resid ? d.specd : d.spec0;
     ta.tw64 = d.p64m; ta.eq64 = d.eq64; ta.tw32 = d.p32m; ta.eq32 = d.eq32;
-    ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.rw_log2 = d.rw_log2;
+    ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2;
     ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.k8 = 0;
     ta.c0 = d.c0; ta.k0tab = d.k0tab;
     ta.fint_w = resid ? nullptr : d.fint_w; ta.fint_out = d.scal;
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_batch(const RhsDesc* __restrict__ descs
         } else if constexpr (STAGE == kBTheta64) {
             ThetaArgs<double> ta{};
             ta.spec = d.spec64; ta.tw = d.p64m; ta.eq = d.eq64;
-            ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.rw_log2 = d.rw_log2;
+            ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2;
             ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.mode = kSolve; ta.k8 = 0;
             ta.c0 = d.c0; ta.k0tab = d.k0tab; ta.fint_w = d.fint_w; ta.fint_out = d.scal;
             theta_body<double, EPT, RMAX, SMAXD>(ta, w.y, smem_raw, red);

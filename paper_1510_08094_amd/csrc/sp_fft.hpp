@@ -223,6 +223,7 @@ constexpr int kMaxPass = 16;
 
 struct FftDesc {
     int N;                 // transform length
+    int fixed;             // a compiled-in fixed transform (FixedFft), or 0
     int npass;
     int radix[kMaxPass];
     int tw_off[kMaxPass];  // offset of each pass's twiddles in the per-pass table
@@ -285,47 +286,115 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- fixed-size transforms
+// The same Stockham passes with the length, the radices, the span Ns of each
+// pass and the number of threads known at compile time: all index arithmetic
+// folds into constants and immediate offsets (the generic passes spend about
+// as many integer as floating-point instructions on it).
+template <typename T, int R, bool INV, int N, int NS, int NT>
+__device__ __forceinline__ void stockham_pass_ct(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int t,
+                                                 bool active) {
+    constexpr int NB = N / R;                 // butterflies
+    constexpr int B = (NB + NT - 1) / NT;     // butterflies per thread; only the last can fall off the end
+    Cx<T> v[B][R];
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * NT;
+            if (b < B - 1 || NB % NT == 0 || j < NB) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NB];
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const unsigned j = (unsigned)(t + b * NT);
+            if (b < B - 1 || NB % NT == 0 || j < (unsigned)NB) {
+                __builtin_assume(j < (unsigned)NB);
+                const unsigned k = NS == 1 ? 0u : j % (unsigned)NS;
+                if constexpr (NS > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        const Cx<T> w = tw[(r - 1) * NS + k];
+                        v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+                    }
+                }
+                dft<T, R, INV>(v[b]);
+                const unsigned base = (j - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[base + r * NS] = v[b][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, bool INV, int N, int NT, int NS, int R, int... REST>
+__device__ __forceinline__ void fft_ct_passes(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int t,
+                                              bool active) {
+    stockham_pass_ct<T, R, INV, N, NS, NT>(buf, tw, t, active);
+    if constexpr (sizeof...(REST) > 0)
+        fft_ct_passes<T, INV, N, NT, NS * R, REST...>(buf, tw + (R - 1) * NS, t, active);
+}
+
+// Fixed transforms compiled in.  A kernel instantiated with the radix-set
+// parameter RMAX = kRadixFixed5000 runs only the fixed passes below; the plan
+// chooses it when FftDesc::fixed says the length, radix order and thread
+// count match.
+enum FixedFft { kFixedNone = 0, kFixed5000 = 1 };
+constexpr int kRadixFixed5000 = -5000;
+constexpr int kFixed5000Threads = 334;   // 5000 = 5^4 8: radix-5 passes with 3 butterflies per thread
+
 // Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
 // radices compiled into this instantiation.
 // The line is base[off .. off + N).
 template <typename T, bool INV, int EPT, int RMAX>
 __device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ base, int off, const FftDesc& d,
                                         const Cx<T>* __restrict__ ptw, int t0, int nthr, bool active) {
-    int Ns = 1;
-    for (int p = 0; p < d.npass; ++p) {
-        const int R = d.radix[p];
-        const Cx<T>* tw = ptw + d.tw_off[p];
-        // The thread index and the line offset are made opaque on every pass:
-        // otherwise the LDS addresses of all radix cases are hoisted out of the
-        // loop and stay live across it, which costs tens of registers and
-        // forces spills.
-        int t = t0, o = off;
-        asm volatile("" : "+v"(t), "+v"(o));
-        Cx<T>* buf = base + o;
-        switch (R) {
-            case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 4: stockham_pass<T, 4, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 5: stockham_pass<T, 5, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 7: stockham_pass<T, 7, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 8: stockham_pass<T, 8, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 11: stockham_pass<T, 11, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 13: stockham_pass<T, 13, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            case 16: stockham_pass<T, 16, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-            default:
-                if constexpr (RMAX >= 17) {
-                    switch (R) {
-                        case 17: stockham_pass<T, 17, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-                        case 19: stockham_pass<T, 19, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-                        case 23: stockham_pass<T, 23, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-                        case 29: stockham_pass<T, 29, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-                        case 31: stockham_pass<T, 31, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
-                        default: break;
+    if constexpr (RMAX == kRadixFixed5000) {
+        (void)d;
+        (void)nthr;
+        fft_ct_passes<T, INV, 5000, kFixed5000Threads, 1, 5, 5, 5, 5, 8>(base + off, ptw, t0, active);
+    } else {
+        int Ns = 1;
+        for (int p = 0; p < d.npass; ++p) {
+            const int R = d.radix[p];
+            const Cx<T>* tw = ptw + d.tw_off[p];
+            // The thread index and the line offset are made opaque on every pass:
+            // otherwise the LDS addresses of all radix cases are hoisted out of the
+            // loop and stay live across it, which costs tens of registers and
+            // forces spills.
+            int t = t0, o = off;
+            asm volatile("" : "+v"(t), "+v"(o));
+            Cx<T>* buf = base + o;
+            switch (R) {
+                case 2: stockham_pass<T, 2, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 3: stockham_pass<T, 3, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 4: stockham_pass<T, 4, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 5: stockham_pass<T, 5, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 7: stockham_pass<T, 7, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 8: stockham_pass<T, 8, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 11: stockham_pass<T, 11, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 13: stockham_pass<T, 13, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                case 16: stockham_pass<T, 16, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                default:
+                    if constexpr (RMAX >= 17) {
+                        switch (R) {
+                            case 17: stockham_pass<T, 17, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                            case 19: stockham_pass<T, 19, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                            case 23: stockham_pass<T, 23, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                            case 29: stockham_pass<T, 29, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                            case 31: stockham_pass<T, 31, INV, EPT>(buf, d.N, Ns, tw, t, nthr, active); break;
+                            default: break;
+                        }
                     }
-                }
-                break;
+                    break;
+            }
+            Ns *= R;
         }
-        Ns *= R;
     }
 }
 

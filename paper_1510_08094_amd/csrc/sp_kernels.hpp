@@ -3,10 +3,11 @@
 // theta pass (cosine/sine transform, banded solves, inverse transform).
 //
 // Spectrum layout in HBM ("j-blocked"): the half spectrum X_k(theta_j),
-// k = 0..N (N = n/2), is stored as spec[((j / RW) * (N + 1) + k) * RW + j % RW]
-// with RW a power of two (rows per lambda workgroup).  A lambda workgroup
-// reads or writes one contiguous block; a theta workgroup reads runs of RW
-// consecutive rows of one wavenumber.
+// k = 0..N (N = n/2), is stored as spec[((j / RL) * (N + 1) + k) * RL + j % RL]
+// with RL = 2^lay a power of two, the run length.  A theta workgroup reads
+// runs of RL consecutive rows of one wavenumber (a 128-byte line for RL = 8 in
+// float64); a lambda workgroup owns RW <= RL rows and writes its part of
+// every run.
 #pragma once
 #include "sp_fft.hpp"
 
@@ -29,7 +30,8 @@ struct LambdaArgs {
     const Cx<T>* tw;        // e^{-2 pi i t/n}, t = 0..n-1 (real-spectrum split)
     const Cx<T>* ptw;       // per-pass twiddles of the length-N complex DFT
     const double* rowscale; // per-row multiplier or nullptr
-    int n, m, N, rw_log2;
+    int n, m, N, rw_log2;   // rw_log2: rows per workgroup (log2)
+    int lay_log2;           // spectrum run length (log2), >= rw_log2
     T w_mid, w_end;         // forward: output weight for 0<k<N and for k in {0,N}; inverse: input weights
     double out_scale;       // inverse: multiplier of the written rows
     FftDesc fft;
@@ -38,8 +40,17 @@ struct LambdaArgs {
 
 // Block layout helpers: a lambda workgroup owns rows jb*RW .. jb*RW+RW-1; row r
 // of the block uses LDS line `lines + r * stride`.
-__device__ __forceinline__ size_t spec_index(int jb, int k, int jj, int N, int rwl) {
-    return (((size_t)jb * (N + 1) + k) << rwl) + jj;
+__device__ __forceinline__ size_t spec_at(int j, int k, int N, int lay) {
+    return ((((size_t)(j >> lay)) * (N + 1) + k) << lay) + (j & ((1 << lay) - 1));
+}
+
+// Lambda workgroup -> row block.  When one spectrum run spans g = 2^glog2 row
+// blocks, the g blocks of a run go to consecutive workgroups of one XCD
+// (workgroups are dealt round-robin over the 8 XCDs), so their writes to the
+// same 128-byte lines meet in that XCD's L2.  The grid is a multiple of 8 g.
+__device__ __forceinline__ int lambda_tile(int glog2) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+    return ((x + ((i >> glog2) << 3)) << glog2) + (i & ((1 << glog2) - 1));
 }
 
 // Split the length-N complex DFT of every row into the half spectrum X_0..X_N
@@ -47,19 +58,20 @@ __device__ __forceinline__ size_t spec_index(int jb, int k, int jj, int N, int r
 // Lanes run over (pair, row) with the row fastest, so stores are contiguous.
 template <typename T, typename TS>
 __device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t stride, Cx<TS>* spec,
-                                                const Cx<T>* tw, int N, int rwl, int m, int jb,
+                                                const Cx<T>* tw, int N, int rwl, int lay, int m, int jb,
                                                 T w_mid, T w_end) {
     const int rw = 1 << rwl;
     const int npairs = N / 2 + 1;
     for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
         const int jj = e & (rw - 1);
         const int k = e >> rwl;
-        if ((jb << rwl) + jj >= m) continue;
+        const int j = (jb << rwl) + jj;
+        if (j >= m) continue;
         const Cx<T>* b = lines + (size_t)jj * stride;
         if (k == 0) {
             const Cx<T> z = b[0];
-            spec[spec_index(jb, 0, jj, N, rwl)] = Cx<TS>{(TS)((z.x + z.y) * w_end), (TS)0};
-            spec[spec_index(jb, N, jj, N, rwl)] = Cx<TS>{(TS)((z.x - z.y) * w_end), (TS)0};
+            spec[spec_at(j, 0, N, lay)] = Cx<TS>{(TS)((z.x + z.y) * w_end), (TS)0};
+            spec[spec_at(j, N, N, lay)] = Cx<TS>{(TS)((z.x - z.y) * w_end), (TS)0};
             continue;
         }
         const Cx<T> zk = b[k], zn = b[N - k];
@@ -67,10 +79,10 @@ __device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t strid
         const Cx<T> O = mul_negi(zk - cconj(zn)) * (T)0.5;
         const Cx<T> WO = cmul(tw[k], O);
         const Cx<T> xk = (E + WO) * w_mid;
-        spec[spec_index(jb, k, jj, N, rwl)] = Cx<TS>{(TS)xk.x, (TS)xk.y};
+        spec[spec_at(j, k, N, lay)] = Cx<TS>{(TS)xk.x, (TS)xk.y};
         if (N - k != k) {
             const Cx<T> xn = cconj(E - WO) * w_mid;
-            spec[spec_index(jb, N - k, jj, N, rwl)] = Cx<TS>{(TS)xn.x, (TS)xn.y};
+            spec[spec_at(j, N - k, N, lay)] = Cx<TS>{(TS)xn.x, (TS)xn.y};
         }
     }
 }
@@ -79,23 +91,24 @@ __device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t strid
 // the length-N complex sequence whose inverse DFT interleaves the real output.
 template <typename T, typename TS>
 __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, const Cx<TS>* spec,
-                                                 const Cx<T>* tw, int N, int rwl, int m, int jb,
+                                                 const Cx<T>* tw, int N, int rwl, int lay, int m, int jb,
                                                  T w_mid, T w_end) {
     const int rw = 1 << rwl;
     const int npairs = N / 2 + 1;
     for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
         const int jj = e & (rw - 1);
         const int k = e >> rwl;
-        if ((jb << rwl) + jj >= m) continue;
+        const int j = (jb << rwl) + jj;
+        if (j >= m) continue;
         Cx<T>* b = lines + (size_t)jj * stride;
         if (k == 0) {
-            const T x0 = (T)spec[spec_index(jb, 0, jj, N, rwl)].x * w_end;
-            const T xN = (T)spec[spec_index(jb, N, jj, N, rwl)].x * w_end;
+            const T x0 = (T)spec[spec_at(j, 0, N, lay)].x * w_end;
+            const T xN = (T)spec[spec_at(j, N, N, lay)].x * w_end;
             b[0] = Cx<T>{x0 + xN, x0 - xN};
             continue;
         }
-        const Cx<TS> sk = spec[spec_index(jb, k, jj, N, rwl)];
-        const Cx<TS> sn = spec[spec_index(jb, N - k, jj, N, rwl)];
+        const Cx<TS> sk = spec[spec_at(j, k, N, lay)];
+        const Cx<TS> sn = spec[spec_at(j, N - k, N, lay)];
         const Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
         const Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
         const Cx<T> P = xk + cconj(xn);
@@ -128,13 +141,15 @@ __device__ __forceinline__ void lambda_fwd_body(const LambdaArgs<T>& a, int jb, 
     }
     __syncthreads();
     fft_lds<T, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
-    r2c_split_store<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
+    r2c_split_store<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, a.w_mid, a.w_end);
 }
 
 template <typename T, int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_fwd(LambdaArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    lambda_fwd_body<T, EPT, RMAX>(a, blockIdx.x, smem_raw);
+    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    if (jb << a.rw_log2 >= a.m) return;
+    lambda_fwd_body<T, EPT, RMAX>(a, jb, smem_raw);
 }
 
 template <typename T, int EPT, int RMAX>
@@ -145,7 +160,7 @@ __device__ __forceinline__ void lambda_inv_body(const LambdaArgs<T>& a, int jb, 
     const int t = threadIdx.x - line * a.nthr;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
-    c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.m, jb, a.w_mid, a.w_end);
+    c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, a.w_mid, a.w_end);
     __syncthreads();
     fft_lds<T, true, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
     if (active) {
@@ -162,7 +177,9 @@ __device__ __forceinline__ void lambda_inv_body(const LambdaArgs<T>& a, int jb, 
 template <typename T, int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_inv(LambdaArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    lambda_inv_body<T, EPT, RMAX>(a, blockIdx.x, smem_raw);
+    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    if (jb << a.rw_log2 >= a.m) return;
+    lambda_inv_body<T, EPT, RMAX>(a, jb, smem_raw);
 }
 
 // ---------------------------------------------------------------- mixed lambda passes
@@ -177,7 +194,7 @@ struct MixLambdaArgs {
     const Cx<double>* ptw64;   // per-pass twiddles of the length-N DFT (float64)
     double* partial;           // per block: sum of correction^2 and of u^2 (or nullptr)
     const double* rowscale;    // update: per-row output multiplier (or nullptr)
-    int n, m, N, rw_log2;
+    int n, m, N, rw_log2, lay_log2;
     float in_w_mid, in_w_end;  // weights of the float32 spectra read by the inverse DFTs
     double mid_scale;          // mix: multiplier of the float32 inverse DFT before the float64 forward DFT
     double out_w_mid, out_w_end; // mix: weights of the float64 spectrum written
@@ -207,7 +224,7 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     // float32 view: row r uses the first N float32 complex slots of its float64 line
     Cx<float>* fl = reinterpret_cast<Cx<float>*>(lines);
-    c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid,
+    c2r_load_prepare<float, float>(fl, 2 * (size_t)N, a.s0, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
                                    a.in_w_end);
     __syncthreads();
     Cx<float>* fbuf = fl + (size_t)line * 2 * N;
@@ -228,13 +245,16 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
     }
     __syncthreads();
     fft_lds<double, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw64, t, a.nthr, active);
-    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.m, jb, a.out_w_mid, a.out_w_end);
+    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.lay_log2, a.m, jb, a.out_w_mid,
+                                    a.out_w_end);
 }
 
 template <int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    lambda_mix_body<EPT, RMAX>(a, blockIdx.x, smem_raw);
+    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    if (jb << a.rw_log2 >= a.m) return;
+    lambda_mix_body<EPT, RMAX>(a, jb, smem_raw);
 }
 
 // u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
@@ -251,8 +271,10 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     const size_t stride = 2 * (size_t)N;
     if (!a.accumulate)
-        c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid, a.in_w_end);
-    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.m, jb, a.in_w_mid, a.in_w_end);
+        c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
+                                       a.in_w_end);
+    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
+                                   a.in_w_end);
     __syncthreads();
     Cx<float>* b0 = fl + (size_t)line * stride;
     Cx<float>* b1 = b0 + N;
@@ -296,7 +318,9 @@ template <int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][16];
-    lambda_update_body<EPT, RMAX>(a, blockIdx.x, smem_raw, red);
+    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    if (jb << a.rw_log2 >= a.m) return;
+    lambda_update_body<EPT, RMAX>(a, jb, smem_raw, red);
 }
 
 // Sum of the per-block partials (one block): out[0] = sum of d^2, out[1] = sum of u^2.
@@ -338,7 +362,8 @@ struct ThetaArgs {
     Cx<T>* spec;
     const Cx<T>* tw;        // per-pass twiddles of the length-m complex DFT
     const Cx<T>* eq;        // e^{-i pi q/(2m)}, q = 0..m-1
-    int n, m, N, rw_log2;
+    const Cx<T>* ws;        // real-part pass: e^{-2 pi i q/m}, q = 0..m/4
+    int n, m, N, lay_log2;  // lay_log2: spectrum run length (log2)
     FftDesc fft;
     int nthr_fft;
     int mode;               // ThetaMode
@@ -349,24 +374,49 @@ struct ThetaArgs {
     double* fint_out;
 };
 
+// Rows of (L - k^2 I) restricted to one parity class, with kk = k^2:
+//   sub = (q-2)(q-1)/4 = q^2/4 - 3q/4 + 1/2,  sup = (q+2)(q+1)/4 = q^2/4 + 3q/4 + 1/2,
+//   diag = -q^2/2 - k^2;
+// the transpose has sub'(q) = sup(q-2) = q^2/4 - q/4 and sup'(q) = sub(q+2) = q^2/4 + q/4.
+// In float64 every value is exact for the sizes supported (q^2 < 2^53).
+template <typename T>
+__device__ __forceinline__ void band_kk(T q, T kk, bool first, bool last, bool transposed, T& sub, T& diag,
+                                        T& sup) {
+    const T qq = q * q;
+    const T base = qq * (T)0.25 + (transposed ? (T)0 : (T)0.5);
+    const T lin = q * (transposed ? (T)0.25 : (T)0.75);
+    diag = qq * (T)-0.5 - kk;
+    sub = first ? (T)0 : base - lin;
+    sup = last ? (T)0 : base + lin;
+}
+
 template <typename T>
 __device__ __forceinline__ void band(int q, int k, bool first, bool last, bool transposed,
                                      T& sub, T& diag, T& sup) {
-    const T qq = (T)q;
-    diag = -(qq * qq) * (T)0.5 - (T)k * (T)k;
-    if (!transposed) {
-        sub = first ? (T)0 : (qq - (T)2) * (qq - (T)1) * (T)0.25;
-        sup = last ? (T)0 : (qq + (T)2) * (qq + (T)1) * (T)0.25;
-    } else {   // rows of the transpose: sub'(q) = sup(q-2), sup'(q) = sub(q+2)
-        sub = first ? (T)0 : qq * (qq - (T)1) * (T)0.25;
-        sup = last ? (T)0 : qq * (qq + (T)1) * (T)0.25;
-    }
+    band_kk<T>((T)q, (T)k * (T)k, first, last, transposed, sub, diag, sup);
 }
+
+// Reciprocals of the pivots (never tiny nor huge here): the hardware estimate
+// refined by two Newton steps in float64 (about one ulp); float32 uses the
+// estimate, which is within one ulp.
+__device__ __forceinline__ double rcp_pivot(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_pivot(float x) { return __builtin_amdgcn_rcpf(x); }
 
 struct ClassInfo {
     int q0, nc, s, p;     // first q, rows, chunk length, chunks
 };
 
+// Chunks of at most SMAX rows, of odd length when possible: the rows of a
+// class sit two line positions apart, so consecutive chunks start 2s
+// positions apart, and an odd s spreads the threads' LDS accesses over the
+// banks (at most two-way conflicts instead of up to 16-way).  The chunk count
+// never exceeds ceil(rows / SMAX), and no chunk is empty.
 template <int SMAX>
 __device__ __forceinline__ ClassInfo make_class(int q0, int qhi) {
     ClassInfo c;
@@ -374,27 +424,62 @@ __device__ __forceinline__ ClassInfo make_class(int q0, int qhi) {
     c.nc = qhi >= q0 ? (qhi - q0) / 2 + 1 : 0;
     c.p = (c.nc + SMAX - 1) / SMAX;
     c.s = c.p ? (c.nc + c.p - 1) / c.p : 0;
+    if ((c.s & 1) == 0 && c.s < SMAX) {
+        c.s += 1;
+        c.p = (c.nc + c.s - 1) / c.s;
+    }
     return c;
 }
 
+// ---------------------------------------------------------------- value types
+// A right-hand side is real (V = T) or complex (V = Cx<T>); the systems are
+// real, so both share the eliminations.
+template <typename V> struct VTraits;
+template <> struct VTraits<double> { using D = double; };
+template <> struct VTraits<float> { using D = double; };
+template <> struct VTraits<Cx<double>> { using D = Cx<double>; };
+template <> struct VTraits<Cx<float>> { using D = Cx<double>; };
+
+template <typename V> __device__ __forceinline__ V vcast(double x) { return (V)x; }
+template <typename V> __device__ __forceinline__ V vcast(float x) { return (V)x; }
+template <typename V> __device__ __forceinline__ V vcast(Cx<double> x) {
+    using T = decltype(V{}.x);
+    return V{(T)x.x, (T)x.y};
+}
+template <typename V> __device__ __forceinline__ V vcast(Cx<float> x) {
+    using T = decltype(V{}.x);
+    return V{(T)x.x, (T)x.y};
+}
+__device__ __forceinline__ double vreal(double v) { return v; }
+__device__ __forceinline__ double vreal(Cx<double> v) { return v.x; }
+template <typename VD> __device__ __forceinline__ VD vfrom_real(double x);
+template <> __device__ __forceinline__ double vfrom_real<double>(double x) { return x; }
+template <> __device__ __forceinline__ Cx<double> vfrom_real<Cx<double>>(double x) { return Cx<double>{x, 0.0}; }
+
 // Partitioned solve of both parity classes for k != 0 (or the transposed
 // systems).  Each thread owns a contiguous chunk of rows of one class: its
-// first row is a separator, the interior rows are eliminated against the two
-// neighbouring separators (spikes v, w), the separators form a tridiagonal
-// system solved by parallel cyclic reduction, and the interiors are rebuilt.
+// first row is a separator, the others are interior rows.  For the interior
+// rows the thread keeps only their right-hand sides and the reciprocal pivots
+// of a top-down elimination.  That elimination gives the last interior row as
+// an affine function of the chunk's separator S and the next separator S+; a
+// bottom-up elimination gives the first interior row the same way.  The
+// separators then form a tridiagonal system, solved by parallel cyclic
+// reduction, and a final forward/backward substitution with S and S+ known
+// rebuilds the interior rows.
+
 // Right-hand-side slot of row ii of a thread's chunk in the "solve order"
 // used for values kept between kernels: class A rows first, then class B,
 // each interleaved over the chunks (consecutive threads, consecutive slots).
-// A class of nc rows in p chunks of s rows uses s p <= nc + p - 1 slots, so
-// the slots of a line (both classes, chunks of at least 12 rows, at most
-// m/12 + 2 chunks) stay below m + m/8 + 16.
-__host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + (m >> 3) + 16; }
+// A class of nc rows in p chunks of s rows (no chunk empty) uses
+// s p < nc + s <= nc + SMAX slots, so with SMAX <= 31 the slots of a line (both
+// classes) stay below m + 64.
+__host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64; }
 
 // load(p, q, slot) returns the right-hand side of the row of coefficient q
-// (LDS position p, solve-order slot); store(p, x) receives the solution.
-// Every load happens before the first barrier and every store after the last
-// use of the LDS scratch.
-template <typename T, int SMAX, typename Load, typename Store>
+// (line position p: q for cosine, m - q for sine; solve-order slot);
+// store(p, x) receives the solution.  Every load happens before the first
+// barrier and every store after the last use of the LDS scratch.
+template <typename T, typename V, int SMAX, typename Load, typename Store>
 __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
                                                      int m, int k, bool sine, bool transposed, int tid) {
     const int qhi = sine ? m : m - 1;
@@ -410,85 +495,86 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     const int lo = p * C.s;
     const int cnt = (inA || inB) ? min(C.s, C.nc - lo) : 0;
     const int ni = cnt - 1;
+    auto lpos = [&](int q) { return sine ? m - q : q; };
+    const T kk = (T)k * (T)k;
+    auto rowband = [&](int row, bool first, T& a, T& b, T& c) {
+        band_kk<T>((T)(C.q0 + 2 * row), kk, first, row == C.nc - 1, transposed, a, b, c);
+    };
 
-    Cx<T> dr[SMAX];
-    T vr[SMAX], cr[SMAX];
-    // load the chunk (LDS position of coefficient q: q for cosine, m - q for sine)
+    V r[SMAX];
+    T iv[SMAX];
     const int slot0 = (inA ? 0 : A.s * A.p) + p;
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            dr[ii] = load(sine ? m - q : q, q, slot0 + ii * C.p);
+            r[ii] = load(lpos(q), q, slot0 + ii * C.p);
         }
     }
-    __syncthreads();   // B1: the column may now be overwritten by scratch
+    __syncthreads();   // B1: the line may now be overwritten by scratch
 
-    T dwlast = 0;
+    // top-down: x_ii = dy - S dv - cp x_{ii+1}; at the last interior row
+    // x = yL - S vL - S+ wL
+    V yL{};
+    T vL = (T)-1, wL = (T)0;   // no interior row: the "last interior row" is the separator
     {
-        T cpp = 0, dvp = 0;
-        Cx<T> dyp{0, 0};
+        T cp = 0, dv = 0;
+        V dy{};
 #pragma unroll
         for (int ii = 1; ii < SMAX; ++ii) {
             if (ii <= ni) {
                 const int row = lo + ii;
-                const int q = C.q0 + 2 * row;
                 T a, b, c;
-                band<T>(q, k, false, row == C.nc - 1, transposed, a, b, c);
-                const T den = (ii == 1) ? b : b - a * cpp;
-                const T inv = (T)1 / den;
-                const T cp = c * inv;
-                const Cx<T> dy = (ii == 1) ? dr[ii] * inv : (dr[ii] - dyp * a) * inv;
-                const T dv = (ii == 1) ? a * inv : -a * dvp * inv;
-                if (ii == ni) dwlast = c * inv;
-                cr[ii] = cp; dr[ii] = dy; vr[ii] = dv;
-                cpp = cp; dyp = dy; dvp = dv;
+                rowband(row, false, a, b, c);
+                const T inv = rcp_pivot(b - a * cp);
+                iv[ii] = inv;
+                cp = c * inv;
+                dy = (r[ii] - dy * a) * inv;
+                dv = (ii == 1 ? a : -a * dv) * inv;
             }
         }
+        if (ni >= 1) { yL = dy; vL = dv; wL = cp; }
     }
+    // bottom-up: x_ii = ey - cq x_{ii-1} - ew S+; at the first interior row
+    // x = yF - S vF - S+ wF
+    V yF{};
+    T vF = (T)0, wF = (T)-1;   // no interior row: the "first interior row" is the next separator
     {
-        Cx<T> yn{0, 0};
-        T vn = 0, wn = 0;
+        T cq = 0, ew = 0;
+        V ey{};
 #pragma unroll
         for (int ii = SMAX - 1; ii >= 1; --ii) {
             if (ii <= ni) {
-                Cx<T> y;
-                T v, w;
-                if (ii == ni) { y = dr[ii]; v = vr[ii]; w = dwlast; }
-                else { y = dr[ii] - yn * cr[ii]; v = vr[ii] - cr[ii] * vn; w = -cr[ii] * wn; }
-                dr[ii] = y; vr[ii] = v; cr[ii] = w;
-                yn = y; vn = v; wn = w;
+                const int row = lo + ii;
+                T a, b, c;
+                rowband(row, false, a, b, c);
+                const T inv = rcp_pivot(b - c * cq);
+                cq = a * inv;
+                ey = (r[ii] - ey * c) * inv;
+                ew = (ii == ni ? c : -c * ew) * inv;
             }
         }
+        if (ni >= 1) { yF = ey; vF = cq; wF = ew; }
     }
-    // first / last interior value triples (a chunk of one row passes the neighbour through)
-    Cx<T> yF{0, 0}, yL{0, 0};
-    T vF = 0, wF = -1, vL = -1, wL = 0;
-    if (ni >= 1) {
-        yF = dr[1]; vF = vr[1]; wF = cr[1];
-#pragma unroll
-        for (int ii = 1; ii < SMAX; ++ii)
-            if (ii == ni) { yL = dr[ii]; vL = vr[ii]; wL = cr[ii]; }
-    }
-    // scratch: de[ptot] (Cx), al[ptot], be[ptot], ga[ptot] (T)
-    Cx<T>* de = reinterpret_cast<Cx<T>*>(scratch);
+    // scratch: de[ptot] (V), al[ptot], be[ptot], ga[ptot] (T)
+    V* de = reinterpret_cast<V*>(scratch);
     T* al = reinterpret_cast<T*>(de + ptot);
     T* be = al + ptot;
     T* ga = be + ptot;
     if (cnt > 0) { de[tid] = yL; al[tid] = vL; ga[tid] = wL; }
     __syncthreads();   // B2
     T nal = 0, nbe = 1, nga = 0;
-    Cx<T> nde{0, 0};
+    V nde{};
     if (cnt > 0) {
         T a0, b0, c0;
-        band<T>(C.q0 + 2 * lo, k, lo == 0, lo == C.nc - 1, transposed, a0, b0, c0);
-        Cx<T> pyL{0, 0};
+        rowband(lo, lo == 0, a0, b0, c0);
+        V pyL{};
         T pvL = 0, pwL = 0;
         if (p > 0) { pyL = de[tid - 1]; pvL = al[tid - 1]; pwL = ga[tid - 1]; }
         nal = -a0 * pvL;
         nbe = b0 - a0 * pwL - c0 * vF;
         nga = -c0 * wF;
-        nde = dr[0] - pyL * a0 - yF * c0;
+        nde = r[0] - pyL * a0 - yF * c0;
     }
     __syncthreads();   // B3
     if (cnt > 0) { al[tid] = nal; be[tid] = nbe; ga[tid] = nga; de[tid] = nde; }
@@ -497,11 +583,11 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     const int pmax = max(A.p, B.p);
     for (int h = 1; h < pmax; h <<= 1) {
         T xal = nal, xbe = nbe, xga = nga;
-        Cx<T> xde = nde;
+        V xde = nde;
         if (cnt > 0) {
             const int im = tid - h, ip = tid + h;
             if (im >= cls_lo) {
-                const T k1 = nal / be[im];
+                const T k1 = nal * rcp_pivot(be[im]);
                 xal = -k1 * al[im];
                 xbe = xbe - k1 * ga[im];
                 xde = xde - de[im] * k1;
@@ -509,7 +595,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
                 xal = 0;
             }
             if (ip < cls_hi) {
-                const T k2 = nga / be[ip];
+                const T k2 = nga * rcp_pivot(be[ip]);
                 xga = -k2 * ga[ip];
                 xbe = xbe - k2 * al[ip];
                 xde = xde - de[ip] * k2;
@@ -522,30 +608,47 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
         if (cnt > 0) { al[tid] = nal; be[tid] = nbe; ga[tid] = nga; de[tid] = nde; }
         __syncthreads();
     }
-    const Cx<T> S = nde * ((T)1 / nbe);
+    const V S = nde * rcp_pivot(nbe);
     if (cnt > 0) de[tid] = S;
     __syncthreads();
-    Cx<T> Sn{0, 0};
+    V Sn{};
     if (cnt > 0 && tid + 1 < cls_hi) Sn = de[tid + 1];
     __syncthreads();   // scratch no longer needed: write the solution
     if (cnt > 0) {
-        store(sine ? m - (C.q0 + 2 * lo) : C.q0 + 2 * lo, S);
+        store(lpos(C.q0 + 2 * lo), S);
+        // interior rows with both separators known: forward, then backward substitution
+        V prev = S;
 #pragma unroll
         for (int ii = 1; ii < SMAX; ++ii) {
             if (ii <= ni) {
-                const int q = C.q0 + 2 * (lo + ii);
-                store(sine ? m - q : q, dr[ii] - S * vr[ii] - Sn * cr[ii]);
+                const int row = lo + ii;
+                T a, b, c;
+                rowband(row, false, a, b, c);
+                r[ii] = (r[ii] - prev * a) * iv[ii];
+                prev = r[ii];
+            }
+        }
+        V next = Sn;
+#pragma unroll
+        for (int ii = SMAX - 1; ii >= 1; --ii) {
+            if (ii <= ni) {
+                const int row = lo + ii;
+                T a, b, c;
+                rowband(row, false, a, b, c);
+                r[ii] = r[ii] - next * (c * iv[ii]);
+                next = r[ii];
+                store(lpos(C.q0 + 2 * row), r[ii]);
             }
         }
     }
 }
 
-// In place on a column held in LDS.
-template <typename T, int SMAX>
-__device__ __forceinline__ void solve_partitioned(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch,
+// In place on a line held in LDS.
+template <typename T, int SMAX, typename V>
+__device__ __forceinline__ void solve_partitioned(V* __restrict__ buf, unsigned char* __restrict__ scratch,
                                                   int m, int k, bool sine, bool transposed, int tid) {
-    solve_partitioned_io<T, SMAX>([&](int p, int, int) { return buf[p]; },
-                                  [&](int p, Cx<T> x) { buf[p] = x; }, scratch, m, k, sine, transposed, tid);
+    solve_partitioned_io<T, V, SMAX>([&](int p, int, int) { return buf[p]; },
+                                     [&](int p, V x) { buf[p] = x; }, scratch, m, k, sine, transposed, tid);
 }
 
 // Block-wide sum of one complex double per thread (result valid in every thread).
@@ -563,6 +666,9 @@ __device__ __forceinline__ Cx<double> block_sum(Cx<double> v, Cx<double>* red) {
     __syncthreads();
     return s;
 }
+__device__ __forceinline__ double block_sum(double v, Cx<double>* red) {
+    return block_sum(Cx<double>{v, 0.0}, red).x;
+}
 
 // k = 0: the two cosine classes (odd q, and even q >= 2) are solved with LU
 // factors precomputed on the host in extended precision (the k = 0 systems
@@ -572,18 +678,18 @@ __device__ __forceinline__ Cx<double> block_sum(Cx<double> v, Cx<double>* red) {
 //   T^T x = r: z_i = r_i - cp_{i-1} z_{i-1},           x_i = (z_i - sub_{i+1} x_{i+1}) inv_i
 // a_0 then follows from the constraint (transposed: the constraint row feeds
 // the even class and the q = 0 output is zero).  Always float64.
-template <int SMAX>
-__device__ __forceinline__ void scan_affine(Cx<double>& A, double& Bm, unsigned char* scratch, int tid,
-                            int cls_lo, int cls_hi, int ptot, bool reverse, bool valid) {
+template <typename VD, int SMAX>
+__device__ __forceinline__ void scan_affine(VD& A, double& Bm, unsigned char* scratch, int tid,
+                                            int cls_lo, int cls_hi, int ptot, bool reverse, bool valid) {
     // inclusive scan of maps f_p(z) = A_p + B_p z over the chunks of a class
     // (forward: f_p applied after f_{p-1}; reverse: after f_{p+1}).
-    Cx<double>* sa = reinterpret_cast<Cx<double>*>(scratch);
+    VD* sa = reinterpret_cast<VD*>(scratch);
     double* sb = reinterpret_cast<double*>(sa + ptot);
     if (valid) { sa[tid] = A; sb[tid] = Bm; }
     __syncthreads();
     const int pmax = ptot;   // upper bound on class length
     for (int h = 1; h < pmax; h <<= 1) {
-        Cx<double> nA = A;
+        VD nA = A;
         double nB = Bm;
         if (valid) {
             const int o = reverse ? tid + h : tid - h;
@@ -600,10 +706,12 @@ __device__ __forceinline__ void scan_affine(Cx<double>& A, double& Bm, unsigned 
     }
 }
 
-template <typename T, int SMAX>
-__device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
-                         bool transposed, double c0, const double* __restrict__ tab, Cx<double>* red,
-                         int tid) {
+// buf holds the line in position order (cosine: position q); V is real or complex.
+template <typename T, int SMAX, typename V>
+__device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
+                                         bool transposed, double c0, const double* __restrict__ tab,
+                                         Cx<double>* red, int tid) {
+    using VD = typename VTraits<V>::D;
     const int qhi = m - 1;
     const ClassInfo A = make_class<SMAX>(2, qhi);   // even q >= 2
     const ClassInfo B = make_class<SMAX>(1, qhi);   // odd q
@@ -618,15 +726,14 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
     const int cnt = (inA || inB) ? min(C.s, C.nc - lo) : 0;
     const double* inv = tab + (inA ? 0 : 2 * A.nc);
     const double* cp = inv + C.nc;
-    const Cx<double> a0bar{(double)buf[0].x, (double)buf[0].y};
+    const VD a0bar = vcast<VD>(buf[0]);
 
-    Cx<double> r[SMAX];
+    VD r[SMAX];
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            const Cx<T> v = buf[q];
-            r[ii] = Cx<double>{(double)v.x, (double)v.y};
+            r[ii] = vcast<VD>(buf[q]);
             if (transposed && inA) {
                 const double om = 1.0 / (1.0 - (double)q * (double)q);
                 r[ii] = r[ii] - a0bar * om;
@@ -640,13 +747,13 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
         return (q - 2.0) * (q - 1.0) * 0.25;
     };
     // forward recurrence z_i = alpha_i + beta_i z_{i-1}
-    Cx<double> Af{0.0, 0.0};
+    VD Af{};
     double Bf = 1.0;
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int row = lo + ii;
-            Cx<double> al;
+            VD al;
             double be;
             if (!transposed) { al = r[ii] * inv[row]; be = -sub_of(row) * inv[row]; }
             else { al = r[ii]; be = row > 0 ? -cp[row - 1] : 0.0; }
@@ -654,17 +761,17 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
             Bf = be * Bf;
         }
     }
-    scan_affine<SMAX>(Af, Bf, scratch, tid, cls_lo, cls_hi, ptot, false, cnt > 0);
+    scan_affine<VD, SMAX>(Af, Bf, scratch, tid, cls_lo, cls_hi, ptot, false, cnt > 0);
     // value entering this chunk = inclusive result of the previous chunk applied to 0
-    Cx<double>* sa = reinterpret_cast<Cx<double>*>(scratch);
-    Cx<double> zin{0.0, 0.0};
+    VD* sa = reinterpret_cast<VD*>(scratch);
+    VD zin{};
     if (cnt > 0 && tid - 1 >= cls_lo) zin = sa[tid - 1];
     __syncthreads();
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int row = lo + ii;
-            Cx<double> al;
+            VD al;
             double be;
             if (!transposed) { al = r[ii] * inv[row]; be = -sub_of(row) * inv[row]; }
             else { al = r[ii]; be = row > 0 ? -cp[row - 1] : 0.0; }
@@ -673,13 +780,13 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
         }
     }
     // backward recurrence x_i = gamma_i + delta_i x_{i+1}
-    Cx<double> Ab{0.0, 0.0};
+    VD Ab{};
     double Bb = 1.0;
 #pragma unroll
     for (int ii = SMAX - 1; ii >= 0; --ii) {
         if (ii < cnt) {
             const int row = lo + ii;
-            Cx<double> ga;
+            VD ga;
             double de;
             if (!transposed) { ga = r[ii]; de = -cp[row]; }
             else { ga = r[ii] * inv[row]; de = row + 1 < C.nc ? -sub_of(row + 1) * inv[row] : 0.0; }
@@ -687,16 +794,16 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
             Bb = de * Bb;
         }
     }
-    scan_affine<SMAX>(Ab, Bb, scratch, tid, cls_lo, cls_hi, ptot, true, cnt > 0);
-    Cx<double> xin{0.0, 0.0};
+    scan_affine<VD, SMAX>(Ab, Bb, scratch, tid, cls_lo, cls_hi, ptot, true, cnt > 0);
+    VD xin{};
     if (cnt > 0 && tid + 1 < cls_hi) xin = sa[tid + 1];
     __syncthreads();
-    Cx<double> part{0.0, 0.0};
+    VD part{};
 #pragma unroll
     for (int ii = SMAX - 1; ii >= 0; --ii) {
         if (ii < cnt) {
             const int row = lo + ii;
-            Cx<double> ga;
+            VD ga;
             double de;
             if (!transposed) { ga = r[ii]; de = -cp[row]; }
             else { ga = r[ii] * inv[row]; de = row + 1 < C.nc ? -sub_of(row + 1) * inv[row] : 0.0; }
@@ -708,32 +815,29 @@ __device__ __forceinline__ void solve_k0(Cx<T>* __restrict__ buf, unsigned char*
             }
         }
     }
-    const Cx<double> dot = block_sum(part, red);
+    const VD dot = block_sum(part, red);
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            buf[q] = Cx<T>{(T)r[ii].x, (T)r[ii].y};
+            buf[q] = vcast<V>(r[ii]);
         }
     }
-    if (tid == 0) {
-        if (!transposed) buf[0] = Cx<T>{(T)(c0 - dot.x), (T)(-dot.y)};
-        else buf[0] = Cx<T>{(T)0, (T)0};
-    }
+    if (tid == 0) buf[0] = transposed ? V{} : vcast<V>(vfrom_real<VD>(c0) - dot);
 }
 
 template <typename T, int EPT, int RMAX, int SMAX>
 __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigned char* smem_raw,
                                            Cx<double>* red) {
     Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
-    const int m = a.m, N = a.N, rwl = a.rw_log2, rw = 1 << rwl;
+    const int m = a.m, N = a.N, lay = a.lay_log2;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
     const T invm = (T)1 / (T)m;
 
     double fpart = 0.0;
     for (int j = tid; j < m; j += nthr) {
-        const size_t idx = ((((size_t)(j >> rwl)) * (N + 1) + k) << rwl) + (j & (rw - 1));
+        const size_t idx = spec_at(j, k, N, lay);
         Cx<T> x = a.spec[idx];
         if (sine && (j & 1)) x = Cx<T>{-x.x, -x.y};
         const int pos = (j & 1) ? m - ((j + 1) >> 1) : (j >> 1);
@@ -789,7 +893,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
     __syncthreads();
     fft_lds<T, true, EPT, RMAX>(buf, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
     for (int j = tid; j < m; j += nthr) {
-        const size_t idx = ((((size_t)(j >> rwl)) * (N + 1) + k) << rwl) + (j & (rw - 1));
+        const size_t idx = spec_at(j, k, N, lay);
         const int pos = (j & 1) ? m - ((j + 1) >> 1) : (j >> 1);
         Cx<T> x = buf[pos] * invm;
         if (sine && (j & 1)) x = Cx<T>{-x.x, -x.y};
@@ -836,7 +940,9 @@ struct ThetaMixArgs {
     const Cx<double>* eq64;
     const Cx<float>* tw32;
     const Cx<float>* eq32;
-    int n, m, N, rw_log2;
+    const Cx<double>* ws64;    // real-part pass: e^{-2 pi i q/m}, q = 0..m/4
+    const Cx<float>* ws32;
+    int n, m, N, lay_log2;
     FftDesc fft;
     int nthr_fft;
     int k8;
@@ -938,12 +1044,12 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
                                                  Cx<double>* red) {
     Cx<double>* bufd = reinterpret_cast<Cx<double>*>(smem_raw);
     Cx<float>* buff = reinterpret_cast<Cx<float>*>(smem_raw);
-    const int m = a.m, N = a.N, rwl = a.rw_log2, rw = 1 << rwl;
+    const int m = a.m, N = a.N, lay = a.lay_log2;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
     const double invm = 1.0 / (double)m;
     auto idx = [&](int j) -> size_t {
-        return ((((size_t)(j >> rwl)) * (N + 1) + k) << rwl) + (j & (rw - 1));
+        return spec_at(j, k, N, lay);
     };
     auto posj = [&](int j) -> int { return (j & 1) ? m - ((j + 1) >> 1) : (j >> 1); };
 
@@ -998,11 +1104,11 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
             return Fk[slot] - ax;
         };
         if (k < a.k64) {   // ill-conditioned low wavenumbers: float64 elimination
-            solve_partitioned_io<double, SMAXD>(
+            solve_partitioned_io<double, Cx<double>, SMAXD>(
                 load, [&](int p, Cx<double> x) { buff[p] = Cx<float>{(float)x.x, (float)x.y}; }, smem_raw, m, k,
                 sine, TRANS, tid);
         } else {
-            solve_partitioned_io<float, SMAXF>(
+            solve_partitioned_io<float, Cx<float>, SMAXF>(
                 [&](int p, int q, int slot) {
                     const Cx<double> r = load(p, q, slot);
                     return Cx<float>{(float)r.x, (float)r.y};

@@ -1,0 +1,351 @@
+// Theta pass on ONE real part (Re or Im) of one wavenumber's column, for even m.
+//
+// The banded systems of Section 5 are real, so the real and imaginary parts
+// of a column X_k(theta_j) are transformed and solved independently.  A
+// workgroup owns one (k, part) pair: its line is m real values (8m bytes in
+// float64), half of a complex column, so two workgroups share a compute unit
+// and one's memory traffic overlaps the other's arithmetic.
+//
+// Cosine transform of a real line x (DCT-II, Makhoul's reordering): v = x
+// permuted (even samples ascending, odd samples descending), V = DFT_m(v),
+// y_q = Re(E_q V_q) with E_q = e^{-i pi q/(2m)}.  The real DFT_m goes through a
+// complex DFT of length M = m/2 of z_p = v_2p + i v_2p+1:
+//   E = (Z_q + conj Z_{M-q})/2,  O = -i (Z_q - conj Z_{M-q})/2,  w = e^{-2 pi i q/m}
+//   V_q = E + w O,  V_{M-q} = conj(E - w O)
+// and, as E_{m-q} = -i conj(E_q), y_{m-q} = -Im(E_q V_q).  One pair (q, M-q)
+// of Z gives the four coefficients q, m-q, M-q, M+q.  The inverse runs the
+// same relations backwards: V_q = conj(E_q)(y_q - i y_{m-q}),
+//   Z_q = (V_q + conj V_{M-q}) + i conj(w) (V_q - conj V_{M-q}),
+// z = IDFT_M(Z) (unnormalised) holds m times v.  The sine case (odd k) is the
+// cosine transform of (-1)^j x_j read backwards, as in the complex kernels.
+// Line positions: coefficient q sits at position q (cosine) or m - q (sine).
+#pragma once
+#include "sp_kernels.hpp"
+
+namespace sp {
+
+constexpr int kRealPairHold = 8;    // coefficient pairs per thread in the split steps
+constexpr int kRealLoadHold = 24;   // line values per thread in the load / residual steps
+
+// Threads of a real-part workgroup must cover the split pairs and the loads.
+__host__ __device__ __forceinline__ int real_theta_min_threads(int m) {
+    const int pairs = (m >> 2) + 1;
+    const int a = (pairs + kRealPairHold - 1) / kRealPairHold;
+    const int b = (m + kRealLoadHold - 1) / kRealLoadHold;
+    return a > b ? a : b;
+}
+
+// z (M complex, after the forward DFT) -> y (m reals, position order), in
+// place; coefficient q times s0 (q = 0) or s1 (q > 0).
+template <typename T>
+__device__ __forceinline__ void rdct_split_forward(Cx<T>* z, const Cx<T>* __restrict__ eq,
+                                                   const Cx<T>* __restrict__ ws, int m, T s0, T s1, int tid,
+                                                   int nthr) {
+    T* y = reinterpret_cast<T*>(z);
+    const int M = m >> 1, P = (M >> 1) + 1;
+    T o[kRealPairHold][4];
+#pragma unroll
+    for (int e = 0; e < kRealPairHold; ++e) {
+        const int q = tid + e * nthr;
+        if (q < P) {
+            const int qq = q == 0 ? 0 : M - q;   // Z_M = Z_0
+            const Cx<T> Zq = z[q], Zqq = z[qq];
+            const Cx<T> Ev = (Zq + cconj(Zqq)) * (T)0.5;
+            const Cx<T> wO = cmul(ws[q], mul_negi(Zq - cconj(Zqq)) * (T)0.5);
+            const Cx<T> Wq = cmul(eq[q], Ev + wO);
+            const Cx<T> Wqq = cmul(eq[M - q], cconj(Ev - wO));
+            o[e][0] = Wq.x;
+            o[e][1] = -Wq.y;
+            o[e][2] = Wqq.x;
+            o[e][3] = -Wqq.y;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRealPairHold; ++e) {
+        const int q = tid + e * nthr;
+        if (q < P) {
+            y[q] = o[e][0] * (q == 0 ? s0 : s1);
+            if (q != 0) y[m - q] = o[e][1] * s1;
+            if (M - q != q) {
+                y[M - q] = o[e][2] * s1;
+                if (q != 0) y[M + q] = o[e][3] * s1;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// y (m reals, position order; coefficient q times s0 / s1) -> Z (M complex), in place.
+template <typename T>
+__device__ __forceinline__ void rdct_split_inverse(T* y, const Cx<T>* __restrict__ eq,
+                                                   const Cx<T>* __restrict__ ws, int m, T s0, T s1, int tid,
+                                                   int nthr) {
+    Cx<T>* z = reinterpret_cast<Cx<T>*>(y);
+    const int M = m >> 1, P = (M >> 1) + 1;
+    Cx<T> o[kRealPairHold][2];
+#pragma unroll
+    for (int e = 0; e < kRealPairHold; ++e) {
+        const int q = tid + e * nthr;
+        if (q < P) {
+            const T yq = y[q] * (q == 0 ? s0 : s1);
+            const T ymq = q == 0 ? (T)0 : y[m - q] * s1;
+            const T yMq = y[M - q] * s1;
+            const T yMpq = y[M + q] * s1;
+            const Cx<T> Vq = cmulc(Cx<T>{yq, -ymq}, eq[q]);
+            const Cx<T> Vqq = cmulc(Cx<T>{yMq, -yMpq}, eq[M - q]);
+            const Cx<T> Pp = Vq + cconj(Vqq);
+            const Cx<T> iwQ = mul_i(cmulc(Vq - cconj(Vqq), ws[q]));
+            o[e][0] = Pp + iwQ;
+            o[e][1] = cconj(Pp - iwQ);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRealPairHold; ++e) {
+        const int q = tid + e * nthr;
+        if (q < P) {
+            z[q] = o[e][0];
+            if (q != 0 && M - q != q) z[M - q] = o[e][1];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int line_pos(int j, int m) { return (j & 1) ? m - ((j + 1) >> 1) : (j >> 1); }
+
+// Load one part of column k (times the sine signs) into the line in Makhoul
+// order; all loads of a thread are issued before the first LDS store.
+template <typename T, typename TS>
+__device__ __forceinline__ double load_part(T* y, const Cx<TS>* __restrict__ spec, int part, int k, int m,
+                                            int N, int lay, bool sine, const double* __restrict__ fint_w,
+                                            int tid, int nthr) {
+    const TS* sp = reinterpret_cast<const TS*>(spec) + part;
+    TS v[kRealLoadHold];
+#pragma unroll
+    for (int e = 0; e < kRealLoadHold; ++e) {
+        const int j = tid + e * nthr;
+        if (j < m) v[e] = sp[2 * spec_at(j, k, N, lay)];
+    }
+    double fpart = 0.0;
+#pragma unroll
+    for (int e = 0; e < kRealLoadHold; ++e) {
+        const int j = tid + e * nthr;
+        if (j < m) {
+            const TS x = (sine && (j & 1)) ? -v[e] : v[e];
+            y[line_pos(j, m)] = (T)x;
+            if (fint_w) fpart += fint_w[j] * (double)x;
+        }
+    }
+    return fpart;
+}
+
+template <typename T, typename TS>
+__device__ __forceinline__ void store_part(const T* y, Cx<TS>* __restrict__ spec, int part, int k, int m, int N,
+                                           int lay, bool sine, T scale, int tid, int nthr) {
+    TS* sp = reinterpret_cast<TS*>(spec) + part;
+    for (int j = tid; j < m; j += nthr) {
+        T x = y[line_pos(j, m)] * scale;
+        if (sine && (j & 1)) x = -x;
+        sp[2 * spec_at(j, k, N, lay)] = (TS)x;
+    }
+}
+
+// Workgroup b -> (k, part): slice b mod 8 of the wavenumbers goes to XCD
+// b mod 8, and the two parts of one wavenumber are neighbours on that XCD, so
+// the halves of every 16-byte spectrum entry meet in its L2.
+__device__ __forceinline__ void real_theta_tile(int k8, int* k, int* part) {
+    const int i = blockIdx.x >> 3;
+    *k = (blockIdx.x & 7) * k8 + (i >> 1);
+    *part = i & 1;
+}
+
+// ---------------------------------------------------------------- float64 / float32 single precision pass
+template <typename T, int EPT, int RMAX, int SMAX>
+__device__ __forceinline__ void theta_real_body(const ThetaArgs<T>& a, int k, int part, unsigned char* smem_raw,
+                                                Cx<double>* red) {
+    T* y = reinterpret_cast<T*>(smem_raw);
+    Cx<T>* z = reinterpret_cast<Cx<T>*>(smem_raw);
+    const int m = a.m, N = a.N;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool sine = (k & 1) != 0;
+    const bool want_fint = k == 0 && part == 0 && a.fint_w != nullptr;
+    const double fpart = load_part<T, T>(y, a.spec, part, k, m, N, a.lay_log2, sine,
+                                         want_fint ? a.fint_w : nullptr, tid, nthr);
+    if (want_fint) {
+        const double s = block_sum(fpart, red);
+        if (tid == 0) *a.fint_out = s;
+    }
+    __syncthreads();
+    fft_lds<T, false, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
+    const bool scale = a.mode == kSolve;
+    const T invm = (T)1 / (T)m;
+    rdct_split_forward<T>(z, a.eq, a.ws, m, scale ? invm : (T)1, scale ? (T)2 * invm : (T)1, tid, nthr);
+    if (a.mode != kTransformOnly) {
+        const bool tr = a.mode == kSolveTransposed;
+        if (k == 0) solve_k0<T, SMAX>(y, smem_raw, m, tr, part == 0 ? a.c0 : 0.0, a.k0tab, red, tid);
+        else solve_partitioned<T, SMAX>(y, smem_raw, m, k, sine, tr, tid);
+        __syncthreads();
+    }
+    rdct_split_inverse<T>(y, a.eq, a.ws, m, scale ? (T)m : (T)1, scale ? (T)m * (T)0.5 : (T)1, tid, nthr);
+    fft_lds<T, true, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
+    store_part<T, T>(y, a.spec, part, k, m, N, a.lay_log2, sine, invm, tid, nthr);
+}
+
+template <typename T, int EPT, int RMAX, int SMAX>
+__global__ void __launch_bounds__(512, 4) k_theta_real(ThetaArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Cx<double> red[8];
+    int k, part;
+    real_theta_tile(a.k8, &k, &part);
+    if (k > a.N) return;
+    theta_real_body<T, EPT, RMAX, SMAX>(a, k, part, smem_raw, red);
+}
+
+// ---------------------------------------------------------------- mixed precision pass
+// k = 0 of the mixed real pass (see theta_mixed_k0 for the complex line): the
+// bordered system in float64, F kept in position order; on return the
+// float32 line yf holds the solution.
+template <int SMAXD, bool RESID, bool TRANS>
+__device__ __forceinline__ void theta_mixed_real_k0(const ThetaMixArgs& a, int part, double* yd, float* yf,
+                                                    double* F, unsigned char* smem_raw, Cx<double>* red,
+                                                    int tid) {
+    const int m = a.m, nthr = blockDim.x;
+    double rh[kRealLoadHold];
+    double r0 = part == 0 ? a.c0 : 0.0;
+    double x0_pin = 0.0;
+    const int qhi = m - 1;
+    if (!RESID) {
+#pragma unroll
+        for (int e = 0; e < kRealLoadHold; ++e) {
+            const int p = tid + e * nthr;
+            if (p < m) {
+                rh[e] = yd[p];
+                F[p] = rh[e];
+            }
+        }
+    } else {
+        double dotp = 0.0;
+        const double b0 = TRANS ? F[0] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kRealLoadHold; ++e) {
+            const int q = tid + e * nthr;
+            if (q < m) {
+                if (q == 0) {
+                    rh[e] = 0.0;
+                    continue;
+                }
+                const int lo_q = (TRANS && (q & 1) == 0) ? 2 : 0;
+                double sub, diag, sup;
+                band<double>(q, 0, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
+                double ax = yd[q] * diag;
+                if (q - 2 >= lo_q) ax += yd[q - 2] * sub;
+                if (q + 2 <= qhi) ax += yd[q + 2] * sup;
+                double rhs = F[q];
+                if (TRANS && (q & 1) == 0) rhs -= b0 * (1.0 / (1.0 - (double)q * (double)q));
+                rh[e] = rhs - ax;
+                if (!TRANS && (q & 1) == 0) dotp += yd[q] * (1.0 / (1.0 - (double)q * (double)q));
+            }
+        }
+        if (!TRANS) {
+            const double dot = block_sum(dotp, red);
+            r0 = r0 - (yd[0] + dot);
+        }
+        if (TRANS) x0_pin = yd[0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRealLoadHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) yd[p] = rh[e];
+    }
+    __syncthreads();
+    solve_k0<double, SMAXD>(yd, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
+    __syncthreads();
+    if (TRANS && RESID && tid == 0) yd[0] = -x0_pin;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRealLoadHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) rh[e] = yd[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRealLoadHold; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) yf[p] = (float)rh[e];
+    }
+    __syncthreads();
+}
+
+// Same refinement as theta_mixed_body, on one real part: float64 analysis
+// of the part (F on the first pass; the current iterate on a correction
+// pass), the right-hand side formed as the solve loads it, float32 (low k:
+// float64) elimination, float32 synthesis written to that part of `out`.
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+__device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int k, int part,
+                                                      unsigned char* smem_raw, Cx<double>* red) {
+    double* yd = reinterpret_cast<double*>(smem_raw);
+    Cx<double>* zd = reinterpret_cast<Cx<double>*>(smem_raw);
+    float* yf = reinterpret_cast<float*>(smem_raw);
+    Cx<float>* zf = reinterpret_cast<Cx<float>*>(smem_raw);
+    const int m = a.m, N = a.N;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool sine = (k & 1) != 0;
+    const bool want_fint = !RESID && k == 0 && part == 0 && a.fint_w != nullptr;
+    const double fpart = load_part<double, double>(yd, RESID ? a.su : a.sa, part, k, m, N, a.lay_log2, sine,
+                                                   want_fint ? a.fint_w : nullptr, tid, nthr);
+    if (want_fint) {
+        const double s = block_sum(fpart, red);
+        if (tid == 0) *a.fint_out = s;
+    }
+    __syncthreads();
+    fft_lds<double, false, EPT, RMAX>(zd, 0, a.fft, a.tw64, tid, a.nthr_fft, tid < a.nthr_fft);
+    const double invm = 1.0 / (double)m;
+    rdct_split_forward<double>(zd, a.eq64, a.ws64, m, TRANS ? 1.0 : invm, TRANS ? 1.0 : 2.0 * invm, tid, nthr);
+
+    const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
+    double* Fk = reinterpret_cast<double*>(a.fco) + (size_t)(2 * k + part) * solve_slot_stride(m);
+    if (k != 0) {
+        auto load = [&](int p, int q, int slot) -> double {
+            if (!RESID) {
+                const double f = yd[p];
+                Fk[slot] = f;
+                return f;
+            }
+            double sub, diag, sup;
+            band<double>(q, k, q - 2 < qlo, q + 2 > qhi, TRANS, sub, diag, sup);
+            double ax = yd[p] * diag;
+            if (q - 2 >= qlo) ax += yd[sine ? p + 2 : p - 2] * sub;
+            if (q + 2 <= qhi) ax += yd[sine ? p - 2 : p + 2] * sup;
+            return Fk[slot] - ax;
+        };
+        if (k < a.k64) {
+            solve_partitioned_io<double, double, SMAXD>(
+                load, [&](int p, double x) { yf[p] = (float)x; }, smem_raw, m, k, sine, TRANS, tid);
+        } else {
+            solve_partitioned_io<float, float, SMAXF>(
+                [&](int p, int q, int slot) { return (float)load(p, q, slot); },
+                [&](int p, float x) { yf[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
+        }
+        __syncthreads();
+    } else {
+        theta_mixed_real_k0<SMAXD, RESID, TRANS>(a, part, yd, yf, Fk, smem_raw, red, tid);
+    }
+    const float fm = (float)m;
+    rdct_split_inverse<float>(yf, a.eq32, a.ws32, m, TRANS ? 1.0f : fm, TRANS ? 1.0f : 0.5f * fm, tid, nthr);
+    fft_lds<float, true, EPT, RMAX>(zf, 0, a.fft, a.tw32, tid, a.nthr_fft, tid < a.nthr_fft);
+    store_part<float, float>(yf, a.out, part, k, m, N, a.lay_log2, sine, 1.0f / fm, tid, nthr);
+}
+
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+__global__ void __launch_bounds__(512, 4) k_theta_mixed_real(ThetaMixArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Cx<double> red[8];
+    int k, part;
+    real_theta_tile(a.k8, &k, &part);
+    if (k > a.N) return;
+    theta_mixed_real_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS>(a, k, part, smem_raw, red);
+}
+
+}  // namespace sp

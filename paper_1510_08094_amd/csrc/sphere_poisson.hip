@@ -21,6 +21,7 @@
 
 #include "../../include/sphere_poisson.h"
 #include "sp_batch.hpp"
+#include "sp_theta_real.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
@@ -41,8 +42,10 @@ int hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 constexpr int kEPT = 16;
-constexpr int kSmaxD = 12;   // chunk rows per thread, float64 solves
-constexpr int kSmaxF = 16;   // chunk rows per thread, float32 solves
+constexpr int kSmaxD = 13;   // chunk rows per thread, float64 solves (odd: see make_class)
+constexpr int kSmaxF = 15;   // chunk rows per thread, float32 solves
+constexpr int kLayLog2 = 3;  // spectrum runs of 8 rows: one 128-byte line per float64 run
+constexpr int kSmaxR = 21;   // chunk rows per thread, real-part theta pass (both precisions)
 
 // ------------------------------------------------------------ twiddles
 // (cos, -sin)(2 pi t / N) in extended precision with exact quadrant
@@ -80,11 +83,13 @@ bool factorize(int L, std::vector<int>& radices) {
         if (!p2.empty()) p2[0] = 16;
         else p2.push_back(2);
     }
-    radices = p2;
+    // odd radices first: the first Stockham pass writes with stride R, which
+    // for an odd R touches distinct LDS banks
     static const int odd[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
     for (int p : odd) {
         while (L % p == 0) { radices.push_back(p); L /= p; }
     }
+    radices.insert(radices.end(), p2.begin(), p2.end());
     return L == 1 && (int)radices.size() <= sp::kMaxPass;
 }
 
@@ -103,6 +108,8 @@ FftDesc make_desc(const std::vector<int>& rad, int L, std::vector<Cx<double>>* t
     FftDesc d{};
     d.N = L;
     d.npass = (int)rad.size();
+    // compiled-in fixed transforms (used when the thread count also matches)
+    if (L == 5000 && rad == std::vector<int>{5, 5, 5, 5, 8}) d.fixed = sp::kFixed5000;
     table->clear();
     long long Ns = 1;
     for (size_t i = 0; i < rad.size(); ++i) {
@@ -150,40 +157,66 @@ template <typename T>
 struct KernelSet {
     void (*fwd)(sp::LambdaArgs<T>);
     void (*inv)(sp::LambdaArgs<T>);
-    void (*theta)(sp::ThetaArgs<T>);
+    void (*theta)(sp::ThetaArgs<T>);        // complex line (odd m), float64 only
+    void (*theta_real)(sp::ThetaArgs<T>);   // one real part per workgroup (even m), float64 only
 };
 
+// RMAX: the radix set compiled into a kernel: 16 (radices up to 16), 32
+// (up to 31) or sp::kRadixFixed5000 (the fixed length-5000 transform).
 template <typename T, int RMAX>
 KernelSet<T> kernel_set() {
-    constexpr int SM = std::is_same<T, double>::value ? kSmaxD : kSmaxF;
-    return KernelSet<T>{&sp::k_lambda_fwd<T, kEPT, RMAX>, &sp::k_lambda_inv<T, kEPT, RMAX>,
-                        &sp::k_theta<T, kEPT, RMAX, SM>};
+    KernelSet<T> k{&sp::k_lambda_fwd<T, kEPT, RMAX>, &sp::k_lambda_inv<T, kEPT, RMAX>, nullptr, nullptr};
+    if constexpr (std::is_same<T, double>::value) {
+        if constexpr (RMAX != sp::kRadixFixed5000) k.theta = &sp::k_theta<double, kEPT, RMAX, kSmaxD>;
+        k.theta_real = &sp::k_theta_real<double, kEPT, RMAX, kSmaxR>;
+    }
+    return k;
 }
 
 template <typename T>
-KernelSet<T> pick_kernels(int rmax) {
-    return rmax <= 16 ? kernel_set<T, 16>() : kernel_set<T, 32>();
+KernelSet<T> pick_kernels(int rs) {
+    if (rs == sp::kRadixFixed5000) return kernel_set<T, sp::kRadixFixed5000>();
+    return rs <= 16 ? kernel_set<T, 16>() : kernel_set<T, 32>();
 }
 
 struct MixedSet {
-    void (*theta_first)(sp::ThetaMixArgs);
-    void (*theta_resid)(sp::ThetaMixArgs);
-    void (*theta_first_t)(sp::ThetaMixArgs);   // transposed systems (adjoint)
-    void (*theta_resid_t)(sp::ThetaMixArgs);
+    // [0] complex line (odd m), [1] one real part per workgroup (even m)
+    void (*theta_first[2])(sp::ThetaMixArgs);
+    void (*theta_resid[2])(sp::ThetaMixArgs);
+    void (*theta_first_t[2])(sp::ThetaMixArgs);   // transposed systems (adjoint)
+    void (*theta_resid_t[2])(sp::ThetaMixArgs);
     void (*mix)(sp::MixLambdaArgs);
     void (*update)(sp::MixLambdaArgs);
 };
 
 template <int RMAX>
 MixedSet mixed_set() {
-    return MixedSet{&sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, false>,
-                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, false>,
-                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, true>,
-                    &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, true>,
-                    &sp::k_lambda_mix<kEPT, RMAX>, &sp::k_lambda_update<kEPT, RMAX>};
+    MixedSet k{{nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, false, false>},
+               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, true, false>},
+               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, false, true>},
+               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, true, true>},
+               &sp::k_lambda_mix<kEPT, RMAX>, &sp::k_lambda_update<kEPT, RMAX>};
+    if constexpr (RMAX != sp::kRadixFixed5000) {
+        k.theta_first[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, false>;
+        k.theta_resid[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, false>;
+        k.theta_first_t[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, true>;
+        k.theta_resid_t[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, true>;
+    }
+    return k;
 }
 
-MixedSet pick_mixed(int rmax) { return rmax <= 16 ? mixed_set<16>() : mixed_set<32>(); }
+MixedSet pick_mixed(int rs) {
+    if (rs == sp::kRadixFixed5000) return mixed_set<sp::kRadixFixed5000>();
+    return rs <= 16 ? mixed_set<16>() : mixed_set<32>();
+}
+
+// The radix set a transform needs (see kernel_set).
+int radix_set(const FftDesc& d, int nthr, bool fixed_ok) {
+    if (fixed_ok && d.fixed == sp::kFixed5000 && nthr == sp::kFixed5000Threads) return sp::kRadixFixed5000;
+    int r = 1;
+    for (int p = 0; p < d.npass; ++p) r = std::max(r, d.radix[p]);
+    return r <= 16 ? 16 : 32;
+}
 
 template <typename T>
 struct Tables {
@@ -191,6 +224,7 @@ struct Tables {
     Cx<T>* pass_n = nullptr; // per-pass twiddles of the length-n/2 DFT
     Cx<T>* pass_m = nullptr; // per-pass twiddles of the length-m DFT
     Cx<T>* eq = nullptr;     // m entries: e^{-i pi q/(2m)}
+    Cx<T>* ws = nullptr;     // m/4 + 1 entries: e^{-2 pi i q/m} (real-part theta pass)
 };
 
 }  // namespace
@@ -200,13 +234,16 @@ struct sp_plan_s {
     sp_desc desc{};
     int device = 0;
     int n = 0, m = 0, N = 0;
-    int rw_log2 = 0;
+    int rw_log2 = 0;          // rows per lambda workgroup (log2)
+    int lay_log2 = 0;         // spectrum run length (log2)
+    int lam_grid = 0;         // lambda workgroups (a multiple of 8 runs when a run spans several)
     int lam_threads = 0;      // threads per row in the lambda kernels
     int theta_threads = 0;    // block size of the theta kernel
     int theta_fft_threads = 0;
+    bool theta_real = false;  // even m: one real part per theta workgroup, DFT length m/2
+    int theta_grid = 0;       // theta workgroups
     size_t lam_lds = 0, theta_lds64 = 0, theta_lds32 = 0;
     int k8 = 0;
-    int rmax = 0;
     FftDesc fft_lam{}, fft_theta{};
     KernelSet<double> kd{};
     KernelSet<float> kf{};
@@ -268,16 +305,18 @@ int validate_desc(const sp_desc* d) {
 
 struct Layout {
     size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32, off_p64n, off_p32n;
+    size_t off_ws64, off_ws32;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
     size_t off_specB, off_spec0, off_specd, off_partial, off_fco;
     size_t spec_elems;
 };
 
-Layout layout_for(int n, int m, int rw, bool mixed) {
+// rw: rows per lambda workgroup; rl: spectrum run length (rows), a multiple of rw
+Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
     Layout L{};
     size_t N = n / 2;
     size_t nblk = (size_t)(m + rw - 1) / rw;
-    L.spec_elems = nblk * (N + 1) * rw;
+    L.spec_elems = ((size_t)(m + rl - 1) / rl) * (N + 1) * rl;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
     L.off_spec = take(L.spec_elems * sizeof(Cx<double>));
@@ -287,6 +326,8 @@ Layout layout_for(int n, int m, int rw, bool mixed) {
     L.off_tw32n = take((size_t)n * sizeof(Cx<float>));
     L.off_tw32m = take((size_t)m * sizeof(Cx<float>));
     L.off_eq32 = take((size_t)m * sizeof(Cx<float>));
+    L.off_ws64 = take((size_t)(m / 4 + 2) * sizeof(Cx<double>));
+    L.off_ws32 = take((size_t)(m / 4 + 2) * sizeof(Cx<float>));
     L.off_p64n = take((size_t)n * sizeof(Cx<double>));
     L.off_p32n = take((size_t)n * sizeof(Cx<float>));
     L.off_sin2 = take((size_t)m * sizeof(double));
@@ -352,8 +393,18 @@ template <typename T>
 void set_lds_attr(const KernelSet<T>& ks, size_t lam, size_t theta) {
     (void)hipFuncSetAttribute((const void*)ks.fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lam);
     (void)hipFuncSetAttribute((const void*)ks.inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lam);
-    (void)hipFuncSetAttribute((const void*)ks.theta, hipFuncAttributeMaxDynamicSharedMemorySize, (int)theta);
+    for (const void* fn : {(const void*)ks.theta, (const void*)ks.theta_real})
+        if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)theta);
     (void)hipGetLastError();
+}
+
+// LDS of the real-part theta pass: the float64 line (m reals) or the solve
+// scratch (separator rows; k = 0 scan values), whichever is larger.
+size_t real_theta_lds_bytes(int m, int ptot) {
+    size_t a = (size_t)m * sizeof(double);
+    size_t b = (size_t)ptot * 4 * sizeof(double);
+    size_t c = (size_t)ptot * 2 * sizeof(double);
+    return (std::max(a, std::max(b, c)) + 15) & ~(size_t)15;
 }
 
 }  // namespace
@@ -413,7 +464,7 @@ extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
     int rwl = 0, nt = 0;
     size_t lds = 0;
     if (!lambda_schedule(d->n_lambda / 2, d->m_theta, rl, 160 * 1024, &rwl, &nt, &lds)) return 0;
-    return layout_for(d->n_lambda, d->m_theta, 1 << rwl, d->precision == SP_MIXED).total;
+    return layout_for(d->n_lambda, d->m_theta, 1 << rwl, 1 << std::max(rwl, kLayLog2), d->precision == SP_MIXED).total;
 }
 
 namespace {
@@ -423,6 +474,8 @@ struct Sched {
     std::vector<int> lam, theta;
     int rw_log2 = -1;
 };
+
+bool valid_radices(const std::vector<int>& r, int L);
 
 int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* out) {
     *out = nullptr;
@@ -440,15 +493,37 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     p->N = p->n / 2;
     const int n = p->n, m = p->m, N = p->N;
 
+    // theta pass: even m runs one real part per workgroup (cosine transform
+    // through a DFT of length m/2) when its thread and LDS budgets allow;
+    // otherwise the complex line (DFT of length m)
+    const size_t static_lds = 16 * sizeof(Cx<double>);
+    if ((m & 1) == 0) {
+        const int M = m / 2, ptotR = solve_threads(m, kSmaxR);
+        std::vector<int> r = sc.theta;
+        if (!valid_radices(r, M)) r.clear();
+        if (r.empty() && !factorize(M, r)) r.clear();
+        if (!r.empty()) {
+            const int fthr = fft_threads(r, M);
+            const int thr = round_up(std::max(std::max(fthr, ptotR), sp::real_theta_min_threads(m)), 64);
+            const size_t lds = real_theta_lds_bytes(m, ptotR);
+            if (thr <= 512 && lds + static_lds <= lds_limit) {
+                p->theta_real = true;
+                p->theta_fft_threads = fthr;
+                p->theta_threads = thr;
+                p->theta_lds64 = lds;
+                p->theta_lds32 = lds;
+            }
+        }
+    }
     std::vector<int> rl = sc.lam, rt = sc.theta;
+    const int Lt = p->theta_real ? m / 2 : m;
+    if (!valid_radices(rl, N)) rl.clear();
+    if (!valid_radices(rt, Lt)) rt.clear();
     if (rl.empty()) factorize(N, rl);
-    if (rt.empty()) factorize(m, rt);
-    p->rmax = 1;
-    for (int r : rl) p->rmax = std::max(p->rmax, r);
-    for (int r : rt) p->rmax = std::max(p->rmax, r);
+    if (rt.empty()) factorize(Lt, rt);
     std::vector<Cx<double>> ptab_n, ptab_m;
     p->fft_lam = make_desc(rl, N, &ptab_n);
-    p->fft_theta = make_desc(rt, m, &ptab_m);
+    p->fft_theta = make_desc(rt, Lt, &ptab_m);
 
     if (!lambda_schedule(N, m, rl, lds_limit, &p->rw_log2, &p->lam_threads, &p->lam_lds)) {
         delete p;
@@ -459,33 +534,50 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         p->rw_log2 = sc.rw_log2;
         p->lam_lds = ((size_t)N << sc.rw_log2) * sizeof(Cx<double>);
     }
-    p->theta_fft_threads = fft_threads(rt, m);
-    int ptotD = solve_threads(m, kSmaxD), ptotF = solve_threads(m, kSmaxF);
-    p->theta_threads = round_up(std::max(std::max(p->theta_fft_threads, ceil_div(m, sp::kThetaHold)),
-                                         std::max(ptotD, ptotF)), 64);
-    p->theta_lds64 = theta_lds_bytes<double>(m, ptotD);
-    p->theta_lds32 = theta_lds_bytes<float>(m, ptotF);
-    const size_t static_lds = 16 * sizeof(Cx<double>);
-    if (p->theta_threads > 1024 || p->theta_lds64 + static_lds > lds_limit) {
-        delete p;
-        return SP_ERR_UNSUPPORTED_SIZE;
+    p->lay_log2 = std::max(p->rw_log2, kLayLog2);
+    {
+        const int nblk = (m + (1 << p->rw_log2) - 1) >> p->rw_log2;
+        p->lam_grid = round_up(nblk, 8 << (p->lay_log2 - p->rw_log2));
+    }
+    if (!p->theta_real) {
+        p->theta_fft_threads = fft_threads(rt, m);
+        int ptotD = solve_threads(m, kSmaxD), ptotF = solve_threads(m, kSmaxF);
+        p->theta_threads = round_up(std::max(std::max(p->theta_fft_threads, ceil_div(m, sp::kThetaHold)),
+                                             std::max(ptotD, ptotF)), 64);
+        p->theta_lds64 = theta_lds_bytes<double>(m, ptotD);
+        p->theta_lds32 = theta_lds_bytes<float>(m, ptotF);
+        if (p->theta_threads > 1024 || p->theta_lds64 + static_lds > lds_limit) {
+            delete p;
+            return SP_ERR_UNSUPPORTED_SIZE;
+        }
     }
     p->k8 = (N + 1 + 7) / 8;
-    p->kd = pick_kernels<double>(p->rmax);
-    p->kf = pick_kernels<float>(p->rmax);
-    p->km = pick_mixed(p->rmax);
+    p->theta_grid = (p->theta_real ? 16 : 8) * p->k8;
+    // lambda and theta kernels are picked separately: either may run a fixed transform
+    const int rs_lam = radix_set(p->fft_lam, p->lam_threads, true);
+    const int rs_th = radix_set(p->fft_theta, p->theta_fft_threads, p->theta_real);
+    {
+        const KernelSet<double> L = pick_kernels<double>(rs_lam), T = pick_kernels<double>(rs_th);
+        p->kd = KernelSet<double>{L.fwd, L.inv, T.theta, T.theta_real};
+        p->kf = pick_kernels<float>(rs_lam);
+        const MixedSet Lm = pick_mixed(rs_lam);
+        p->km = pick_mixed(rs_th);
+        p->km.mix = Lm.mix;
+        p->km.update = Lm.update;
+    }
     set_lds_attr(p->kd, p->lam_lds, p->theta_lds64);
     set_lds_attr(p->kf, p->lam_lds, p->theta_lds64);
-    for (const void* fn : {(const void*)p->km.theta_first, (const void*)p->km.theta_resid,
-                           (const void*)p->km.theta_first_t, (const void*)p->km.theta_resid_t})
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
+    for (int v = 0; v < 2; ++v)
+        for (const void* fn : {(const void*)p->km.theta_first[v], (const void*)p->km.theta_resid[v],
+                               (const void*)p->km.theta_first_t[v], (const void*)p->km.theta_resid_t[v]})
+            if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
     (void)hipGetLastError();
 
     // ---- device memory
     const bool mixed = d->precision == SP_MIXED;
-    Layout L = layout_for(n, m, 1 << p->rw_log2, mixed);
+    Layout L = layout_for(n, m, 1 << p->rw_log2, 1 << p->lay_log2, mixed);
     p->spec_elems = L.spec_elems;
     hipError_t e = hipMalloc(&p->block, L.total);
     if (e != hipSuccess) {
@@ -502,6 +594,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     p->t32.tw_n = (Cx<float>*)(b + L.off_tw32n);
     p->t32.pass_m = (Cx<float>*)(b + L.off_tw32m);
     p->t32.eq = (Cx<float>*)(b + L.off_eq32);
+    p->t64.ws = (Cx<double>*)(b + L.off_ws64);
+    p->t32.ws = (Cx<float>*)(b + L.off_ws32);
     p->t64.pass_n = (Cx<double>*)(b + L.off_p64n);
     p->t32.pass_n = (Cx<float>*)(b + L.off_p32n);
     p->sin2 = (double*)(b + L.off_sin2);
@@ -526,7 +620,10 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         for (size_t i = 0; i < v.size(); ++i) o[i] = Cx<float>{(float)v[i].x, (float)v[i].y};
         return o;
     };
+    std::vector<Cx<double>> ws(m / 4 + 1);
+    for (int q = 0; q <= m / 4; ++q) cis_neg(q, m, &ws[q].x, &ws[q].y);
     std::vector<Cx<float>> twn32 = to32(twn), eq32 = to32(eq), pn32 = to32(ptab_n), pm32 = to32(ptab_m);
+    std::vector<Cx<float>> ws32 = to32(ws);
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
     };
@@ -537,6 +634,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     if (ee == hipSuccess) ee = up(p->t32.tw_n, twn32.data(), n * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->t32.pass_m, pm32.data(), pm32.size() * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->t32.eq, eq32.data(), m * sizeof(Cx<float>));
+    if (ee == hipSuccess) ee = up(p->t64.ws, ws.data(), ws.size() * sizeof(Cx<double>));
+    if (ee == hipSuccess) ee = up(p->t32.ws, ws32.data(), ws32.size() * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->t64.pass_n, ptab_n.data(), ptab_n.size() * sizeof(Cx<double>));
     if (ee == hipSuccess) ee = up(p->t32.pass_n, pn32.data(), pn32.size() * sizeof(Cx<float>));
     if (ee == hipSuccess) ee = up(p->sin2, sin2.data(), m * sizeof(double));
@@ -556,7 +655,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
 
 // ------------------------------------------------------------ autotuner
 // Per transform length: the lambda transform of n (radix order and rows per
-// tile, any precision) and the theta transform of m (radix order, per
+// tile, any precision) and the theta transform of m (radix order of its DFT,
+// length m/2 for even m and m for odd m, per
 // precision).  Candidates are timed with HIP events on scratch problems; the
 // fastest schedules are kept in a text cache, one line per entry:
 //   <arch> lam <n> <rw_log2> <r1,r2,...>      <arch> theta <m> <precision> <r1,r2,...>
@@ -761,7 +861,8 @@ int autotune(const sp_desc* d, hipStream_t s) {
         b.flags = 0;
         Sched best;
         float best_ms = 1e30f;
-        for (auto& r : radix_candidates(m)) {
+        // even m: the real-part theta pass transforms length m/2
+        for (auto& r : radix_candidates((m & 1) ? m : m / 2)) {
             Sched sc;
             sc.theta = r;
             const float ms = time_schedule(b, sc, s, x, y);
@@ -795,7 +896,7 @@ Sched cached_schedule(int n, int m, int prec) {
     it = g_tune.find(key_theta(m, prec));
     if (it != g_tune.end()) {
         std::vector<int> r = parse_radices(it->second);
-        if (valid_radices(r, m)) sc.theta = r;
+        if (valid_radices(r, m) || ((m & 1) == 0 && valid_radices(r, m / 2))) sc.theta = r;
     }
     return sc;
 }
@@ -921,7 +1022,7 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     la.spec = p->spec64;
     la.tw = p->t64.tw_n;
     la.ptw = p->t64.pass_n;
-    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2;
+    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.lay_log2 = p->lay_log2;
     la.fft = p->fft_lam;
     la.nthr = p->lam_threads;
     // forward lambda
@@ -930,14 +1031,15 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     else { la.w_mid = 2.0; la.w_end = 1.0; }
     {
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
-        hipLaunchKernelGGL(p->kd.fwd, dim3(nblk), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(p->lam_grid), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
     }
     // theta
     sp::ThetaArgs<double> ta{};
     ta.spec = p->spec64;
     ta.tw = p->t64.pass_m;
     ta.eq = p->t64.eq;
-    ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2;
+    ta.ws = p->t64.ws;
+    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2;
     ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads;
     ta.mode = mode;
@@ -948,14 +1050,15 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     ta.fint_out = p->scal;
     {
         ProfScope ps(p, SP_KERNEL_THETA, s);
-        hipLaunchKernelGGL(p->kd.theta, dim3(8 * p->k8), dim3(p->theta_threads), p->theta_lds64, s, ta);
+        hipLaunchKernelGGL(p->theta_real ? p->kd.theta_real : p->kd.theta, dim3(p->theta_grid),
+                           dim3(p->theta_threads), p->theta_lds64, s, ta);
     }
     // inverse lambda
     if (!adjoint_weights) { la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0; la.rowscale = nullptr; }
     else { la.w_mid = 0.5; la.w_end = 1.0; la.out_scale = 1.0 / n; la.rowscale = p->sin2; }
     {
         ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
-        hipLaunchKernelGGL(p->kd.inv, dim3(nblk), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
+        hipLaunchKernelGGL(p->kd.inv, dim3(p->lam_grid), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -989,15 +1092,17 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     const int rw = 1 << p->rw_log2;
     const int nblk = (m + rw - 1) / rw;
     const bool want = (p->desc.flags & SP_SYNC_INFO) != 0;
-    const dim3 lam_grid(nblk), lam_block(round_up(rw * p->lam_threads, 64));
-    const dim3 th_grid(8 * p->k8), th_block(p->theta_threads);
+    const dim3 lam_grid(p->lam_grid), lam_block(round_up(rw * p->lam_threads, 64));
+    const dim3 th_grid(p->theta_grid), th_block(p->theta_threads);
+    const int tv = p->theta_real ? 1 : 0;
     // 1. float64 lambda transform of sin^2 f -> spec64
     sp::LambdaArgs<double> la{};
     // forward: sin^2 f with weight 1/n; adjoint: the transpose of the inverse real DFT
     // (weights 2 for 0 < k < n/2, 1 at the ends, no sin^2)
     la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n;
     la.rowscale = adjoint ? nullptr : p->sin2;
-    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.fft = p->fft_lam; la.nthr = p->lam_threads;
+    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.lay_log2 = p->lay_log2; la.fft = p->fft_lam;
+    la.nthr = p->lam_threads;
     la.w_mid = adjoint ? 2.0 : 1.0 / n;
     la.w_end = adjoint ? 1.0 : 1.0 / n;
     {
@@ -1008,13 +1113,14 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     sp::ThetaMixArgs ta{};
     ta.sa = p->spec64; ta.fco = p->fco; ta.su = p->specB; ta.out = p->spec0;
     ta.tw64 = p->t64.pass_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.pass_m; ta.eq32 = p->t32.eq;
-    ta.n = n; ta.m = m; ta.N = N; ta.rw_log2 = p->rw_log2; ta.fft = p->fft_theta;
+    ta.ws64 = p->t64.ws; ta.ws32 = p->t32.ws;
+    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2; ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
     ta.fint_w = p->fint_w; ta.fint_out = p->scal;
     ta.k64 = p->desc.low_k_fp64 < 0 ? std::max(16, m / 64) : std::max(1, p->desc.low_k_fp64);
     {
         ProfScope ps(p, SP_KERNEL_THETA, s);
-        hipLaunchKernelGGL(adjoint ? p->km.theta_first_t : p->km.theta_first, th_grid, th_block, p->theta_lds64,
+        hipLaunchKernelGGL(adjoint ? p->km.theta_first_t[tv] : p->km.theta_first[tv], th_grid, th_block, p->theta_lds64,
                            s, ta);
     }
     const int R = p->desc.max_refine;
@@ -1022,7 +1128,8 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
         sp::LambdaArgs<float> lf{};
         lf.y = u; lf.spec = p->spec0; lf.tw = p->t32.tw_n; lf.ptw = p->t32.pass_n;
         lf.rowscale = adjoint ? p->sin2 : nullptr;
-        lf.n = n; lf.m = m; lf.N = N; lf.rw_log2 = p->rw_log2; lf.fft = p->fft_lam; lf.nthr = p->lam_threads;
+        lf.n = n; lf.m = m; lf.N = N; lf.rw_log2 = p->rw_log2; lf.lay_log2 = p->lay_log2; lf.fft = p->fft_lam;
+        lf.nthr = p->lam_threads;
         lf.w_mid = adjoint ? 0.5f : 1.0f; lf.w_end = 1.0f; lf.out_scale = adjoint ? 1.0 / n : 1.0;
         ProfScope ps(p, SP_KERNEL_LAMBDA_INV, s);
         hipLaunchKernelGGL(p->kf.inv, lam_grid, lam_block, p->lam_lds, s, lf);
@@ -1031,7 +1138,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
         ma.s0 = p->spec0; ma.sd = p->specd; ma.su = p->specB; ma.u = u;
         ma.tw32 = p->t32.tw_n; ma.tw64 = p->t64.tw_n; ma.partial = want ? p->partial : nullptr;
         ma.ptw32 = p->t32.pass_n; ma.ptw64 = p->t64.pass_n;
-        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2;
+        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2; ma.lay_log2 = p->lay_log2;
         ma.fft = p->fft_lam; ma.nthr = p->lam_threads; ma.accumulate = 0;
         if (!adjoint) {
             ma.in_w_mid = 1.0f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0;
@@ -1060,7 +1167,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
             }
             {
                 ProfScope ps(p, SP_KERNEL_THETA_RESID, s);
-                hipLaunchKernelGGL(adjoint ? p->km.theta_resid_t : p->km.theta_resid, th_grid, th_block,
+                hipLaunchKernelGGL(adjoint ? p->km.theta_resid_t[tv] : p->km.theta_resid[tv], th_grid, th_block,
                                    p->theta_lds64, s, ta);
             }
             ma.accumulate = it > 1 ? 1 : 0;
@@ -1192,6 +1299,9 @@ BatchKernels batch_kernels() {
 // rl / rt: radix orders (empty: fixed rule)
 bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, int* rwl, int* lam_nthr,
                     int* th_fft) {
+    // the batch runs the complex-line theta pass: its DFT has length m
+    if (!valid_radices(rl, n / 2)) rl.clear();
+    if (!valid_radices(rt, m)) rt.clear();
     if (rl.empty() && !factorize(n / 2, rl)) return false;
     if (rt.empty() && !factorize(m, rt)) return false;
     const int N = n / 2;
@@ -1359,7 +1469,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         const SizeTables& L = lam[lkey[r]];
         const SizeTables& T = th[tkey[r]];
         sp::RhsDesc& d = descs[r];
-        d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r];
+        d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r]; d.lay_log2 = rwl[r];
         d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r];
         d.k64 = std::max(16, m[r] / 64);
         d.c0 = 0.0;

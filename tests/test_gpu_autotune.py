@@ -49,4 +49,6 @@ def test_autotune_fills_cache_and_stays_correct(tmp_path):
     for l in lines:
         radices = [int(x) for x in l.split()[-1].split(":")[-1].split(",")]
         size = int(l.split()[2])
-        assert int(np.prod(radices)) == (size // 2 if " lam " in l else size)
+        # lambda: a DFT of length n/2; theta: length m/2 for even m (one real part
+        # per workgroup), m for odd m
+        assert int(np.prod(radices)) == (size // 2 if (" lam " in l or size % 2 == 0) else size)

@@ -48,7 +48,9 @@ def test_batch_matches_single_and_oracle(P, precision, tol):
         plan = P.SpherePoisson(n, m, precision)
         single = host(plan.solve(fg[r]))
         plan.close()
-        assert rel2(u, single) <= 1e-14, (r, n, m)
+        # the batch runs the complex-line theta kernels; a single plan with even m
+        # runs one real part per workgroup (different rounding, same solution)
+        assert rel2(u, single) <= (1e-13 if precision == "fp64" else 1e-12), (r, n, m)
         assert rel2(u, O.solve_reduced(f)) <= tol, (r, n, m)
     # a second call with the same sizes and pointers replays the cached graph
     again = [host(u) for u in P.solve_batch(fg, precision)]
