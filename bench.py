@@ -54,6 +54,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def source_digest() -> str:
+    """sha256 of the HIP sources: a measured traffic record applies only to the
+    kernels it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1510_08094_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, precision: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
+    copy), or None when no record matches these kernel sources."""
+    import re
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = source_digest()
+    pat = re.compile(r"traffic-record kernel=(\S+) precision=(\S+) workload=(\S+) fetch_bytes=(\d+) "
+                     r"write_bytes=(\d+) source_sha256=([0-9a-f]+)")
+    for name in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, name), errors="replace") as fh:
+            for line in fh:
+                m = pat.search(line)
+                if m and m.group(1) == kernel and m.group(2) == precision and m.group(3) == workload \
+                        and m.group(6) == digest:
+                    return int(m.group(4)) + int(m.group(5))
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +190,8 @@ def main():
         "config": {"workload": args.workload, "n_lambda": n, "m_theta": m, "dof": dof, "l_max": L,
                    "precision": args.precision, "rhs": 1},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, args.precision, args.workload)},
         "kernels": kernels,
         "paper_context_dof_per_s": 1e8 / 60.0,
     }
