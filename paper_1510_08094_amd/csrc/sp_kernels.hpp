@@ -504,12 +504,16 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     V r[SMAX];
     T iv[SMAX];
     const int slot0 = (inA ? 0 : A.s * A.p) + p;
+    // Branch-free, so that every load of the chunk is issued before the first
+    // use: rows past the chunk re-read the chunk's first row, and idle threads
+    // (always of class B) re-read the first row of class B, with that row's
+    // own slot, so a load that also stores writes the owner's value again.
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
-        if (ii < cnt) {
-            const int q = C.q0 + 2 * (lo + ii);
-            r[ii] = load(lpos(q), q, slot0 + ii * C.p);
-        }
+        const int iic = ii < cnt ? ii : 0;
+        const int row = cnt > 0 ? lo + iic : 0;
+        const int q = C.q0 + 2 * row;
+        r[ii] = load(lpos(q), q, cnt > 0 ? slot0 + iic * C.p : A.s * A.p);
     }
     __syncthreads();   // B1: the line may now be overwritten by scratch
 

@@ -25,7 +25,7 @@
 namespace sp {
 
 constexpr int kRealPairHold = 8;    // coefficient pairs per thread in the split steps
-constexpr int kRealLoadHold = 24;   // line values per thread in the load / residual steps
+constexpr int kRealLoadHold = 24;   // line values per thread (at least m / threads) in the k = 0 steps
 
 // Threads of a real-part workgroup must cover the split pairs and the loads.
 __host__ __device__ __forceinline__ int real_theta_min_threads(int m) {
@@ -115,26 +115,35 @@ __device__ __forceinline__ void rdct_split_inverse(T* y, const Cx<T>* __restrict
 __device__ __forceinline__ int line_pos(int j, int m) { return (j & 1) ? m - ((j + 1) >> 1) : (j >> 1); }
 
 // Load one part of column k (times the sine signs) into the line in Makhoul
-// order; all loads of a thread are issued before the first LDS store.
+// order; all loads of a thread are issued before the first LDS store.  The
+// block size is a multiple of 64 and of the run length, so the rows
+// j = tid + e nthr of a thread share j mod 2^lay and the parity of j: the
+// spectrum index and the line position advance by fixed strides.
 template <typename T, typename TS>
 __device__ __forceinline__ double load_part(T* y, const Cx<TS>* __restrict__ spec, int part, int k, int m,
                                             int N, int lay, bool sine, const double* __restrict__ fint_w,
                                             int tid, int nthr) {
-    const TS* sp = reinterpret_cast<const TS*>(spec) + part;
-    TS v[kRealLoadHold];
-#pragma unroll
-    for (int e = 0; e < kRealLoadHold; ++e) {
-        const int j = tid + e * nthr;
-        if (j < m) v[e] = sp[2 * spec_at(j, k, N, lay)];
-    }
+    constexpr int kBatch = 8;   // loads in flight per thread
+    const TS* sp = reinterpret_cast<const TS*>(spec) + part + 2 * spec_at(tid, k, N, lay);
+    const size_t dj = (size_t)2 * (((size_t)(nthr >> lay) * (N + 1)) << lay);
+    const bool odd = (tid & 1) != 0;
+    const int dp = odd ? -(nthr >> 1) : (nthr >> 1);
+    T* yp = y + line_pos(tid, m);
+    const double* fw = fint_w ? fint_w + tid : nullptr;
+    const int rows = tid < m ? (m - 1 - tid) / nthr + 1 : 0;
     double fpart = 0.0;
+    for (int e0 = 0; e0 < rows; e0 += kBatch) {
+        TS v[kBatch];
 #pragma unroll
-    for (int e = 0; e < kRealLoadHold; ++e) {
-        const int j = tid + e * nthr;
-        if (j < m) {
-            const TS x = (sine && (j & 1)) ? -v[e] : v[e];
-            y[line_pos(j, m)] = (T)x;
-            if (fint_w) fpart += fint_w[j] * (double)x;
+        for (int e = 0; e < kBatch; ++e)
+            if (e0 + e < rows) v[e] = sp[(e0 + e) * dj];
+#pragma unroll
+        for (int e = 0; e < kBatch; ++e) {
+            if (e0 + e < rows) {
+                const TS x = (sine && odd) ? -v[e] : v[e];
+                yp[(e0 + e) * dp] = (T)x;
+                if (fw) fpart += fw[(e0 + e) * nthr] * (double)x;
+            }
         }
     }
     return fpart;
@@ -143,12 +152,13 @@ __device__ __forceinline__ double load_part(T* y, const Cx<TS>* __restrict__ spe
 template <typename T, typename TS>
 __device__ __forceinline__ void store_part(const T* y, Cx<TS>* __restrict__ spec, int part, int k, int m, int N,
                                            int lay, bool sine, T scale, int tid, int nthr) {
-    TS* sp = reinterpret_cast<TS*>(spec) + part;
-    for (int j = tid; j < m; j += nthr) {
-        T x = y[line_pos(j, m)] * scale;
-        if (sine && (j & 1)) x = -x;
-        sp[2 * spec_at(j, k, N, lay)] = (TS)x;
-    }
+    TS* sp = reinterpret_cast<TS*>(spec) + part + 2 * spec_at(tid, k, N, lay);
+    const size_t dj = (size_t)2 * (((size_t)(nthr >> lay) * (N + 1)) << lay);
+    const bool odd = (tid & 1) != 0;
+    const int p0 = line_pos(tid, m), dp = odd ? -(nthr >> 1) : (nthr >> 1);
+    const T sc = (sine && odd) ? -scale : scale;
+    int e = 0;
+    for (int j = tid; j < m; j += nthr, ++e) sp[e * dj] = (TS)(y[p0 + e * dp] * sc);
 }
 
 // Workgroup b -> (k, part): slice b mod 8 of the wavenumbers goes to XCD
