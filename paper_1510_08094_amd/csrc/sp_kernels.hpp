@@ -119,6 +119,24 @@ __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, co
     }
 }
 
+// x_{2i}, x_{2i+1} (one double2 per complex input) times s into buf[i] for
+// i = t, t + nthr, ... < N, eight loads in flight per thread (branch-free:
+// the last one is re-read).
+template <typename T>
+__device__ __forceinline__ void load_row(Cx<T>* buf, const double2* __restrict__ src, double s, int t, int nthr,
+                                         int N) {
+    constexpr int kB = 8;
+    const int cnt = t < N ? (N - 1 - t) / nthr + 1 : 0;
+    for (int e0 = 0; e0 < cnt; e0 += kB) {
+        double2 v[kB];
+#pragma unroll
+        for (int e = 0; e < kB; ++e) v[e] = src[t + min(e0 + e, cnt - 1) * nthr];
+#pragma unroll
+        for (int e = 0; e < kB; ++e)
+            if (e0 + e < cnt) buf[t + (e0 + e) * nthr] = Cx<T>{(T)(v[e].x * s), (T)(v[e].y * s)};
+    }
+}
+
 // Each kernel is a __device__ body taking its tile index (a block of rows, or
 // one wavenumber) and its LDS; the __global__ wrappers map blockIdx to the
 // tile, the batch kernels take tiles from a work list.
@@ -133,11 +151,7 @@ __device__ __forceinline__ void lambda_fwd_body(const LambdaArgs<T>& a, int jb, 
     Cx<T>* buf = lines + (size_t)line * N;
     if (active) {
         const double s = a.rowscale ? a.rowscale[j] : 1.0;
-        const double2* src = reinterpret_cast<const double2*>(a.x + (size_t)j * a.n);
-        for (int i = t; i < N; i += a.nthr) {
-            const double2 p = src[i];
-            buf[i] = Cx<T>{(T)(p.x * s), (T)(p.y * s)};
-        }
+        load_row<T>(buf, reinterpret_cast<const double2*>(a.x + (size_t)j * a.n), s, t, a.nthr, N);
     }
     __syncthreads();
     fft_lds<T, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
