@@ -8,12 +8,14 @@
 // (kernel boundaries order and publish the memory of every XCD).
 #pragma once
 #include "sp_kernels.hpp"
+#include "sp_theta_real.hpp"
 
 namespace sp {
 
 struct RhsDesc {
     int n, m, N, rw_log2, lay_log2;
     int lam_nthr, theta_nthr_fft, k64;
+    int theta_real;    // 1: one real part per theta tile (even m, DFT length m/2); 0: complex line
     double c0;
     FftDesc fl, ft;
     const double* f;
@@ -31,6 +33,8 @@ struct RhsDesc {
     const Cx<float>* p32m;
     const Cx<double>* eq64;
     const Cx<float>* eq32;
+    const Cx<double>* ws64;   // real-part split twiddles e^{-2 pi i q/m}, q <= m/4
+    const Cx<float>* ws32;
     const double* sin2;
     const double* k0tab;
     const double* fint_w;
@@ -49,31 +53,55 @@ enum BatchStage {
     kBStages = 7
 };
 
-__device__ __forceinline__ LambdaArgs<double> lam_args(const RhsDesc& d) {
+// Stage arguments of one problem, built on the host and kept in device
+// memory.  The kernels read them in place through a wave-uniform index, so
+// every field (the transform descriptor's per-pass radix table included) is
+// loaded by the scalar unit; a private copy would put the dynamically indexed
+// pass table in per-lane scratch memory.
+inline LambdaArgs<double> batch_lambda_args(const RhsDesc& d, bool forward) {
     LambdaArgs<double> la{};
     la.n = d.n; la.m = d.m; la.N = d.N; la.rw_log2 = d.rw_log2; la.lay_log2 = d.lay_log2;
     la.fft = d.fl; la.nthr = d.lam_nthr;
     la.tw = d.tw64n; la.ptw = d.p64n;
+    la.spec = d.spec64;
+    if (forward) {
+        la.x = d.f; la.rowscale = d.sin2;
+        la.w_mid = 1.0 / d.n; la.w_end = 1.0 / d.n;
+    } else {
+        la.y = d.u; la.rowscale = nullptr;
+        la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0;
+    }
     return la;
 }
 
-__device__ __forceinline__ MixLambdaArgs mix_args(const RhsDesc& d) {
+inline ThetaArgs<double> batch_theta_args(const RhsDesc& d) {
+    ThetaArgs<double> ta{};
+    ta.spec = d.spec64; ta.spec_out = d.spec64; ta.tw = d.p64m; ta.eq = d.eq64; ta.ws = d.ws64;
+    ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2; ta.lay_out_log2 = d.lay_log2;
+    ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.mode = kSolve; ta.k8 = 0;
+    ta.c0 = d.c0; ta.k0tab = d.k0tab; ta.fint_w = d.fint_w; ta.fint_out = d.scal;
+    return ta;
+}
+
+inline MixLambdaArgs batch_mix_args(const RhsDesc& d) {
     MixLambdaArgs ma{};
     ma.s0 = d.spec0; ma.sd = d.specd; ma.su = d.specB; ma.u = d.u;
     ma.tw32 = d.tw32n; ma.tw64 = d.tw64n; ma.ptw32 = d.p32n; ma.ptw64 = d.p64n;
     ma.partial = d.partial; ma.rowscale = nullptr;
     ma.n = d.n; ma.m = d.m; ma.N = d.N; ma.rw_log2 = d.rw_log2; ma.lay_log2 = d.lay_log2;
+    ma.lay_out_log2 = d.lay_log2;
     ma.in_w_mid = 1.0f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0;
     ma.out_w_mid = 1.0 / d.n; ma.out_w_end = 1.0 / d.n; ma.out_scale = 1.0;
     ma.fft = d.fl; ma.nthr = d.lam_nthr; ma.accumulate = 0;
     return ma;
 }
 
-__device__ __forceinline__ ThetaMixArgs theta_mix_args(const RhsDesc& d, bool resid) {
+inline ThetaMixArgs batch_theta_mix_args(const RhsDesc& d, bool resid) {
     ThetaMixArgs ta{};
     ta.sa = d.spec64; ta.fco = d.fco; ta.su = d.specB; ta.out = resid ? d.specd : d.spec0;
     ta.tw64 = d.p64m; ta.eq64 = d.eq64; ta.tw32 = d.p32m; ta.eq32 = d.eq32;
-    ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2;
+    ta.ws64 = d.ws64; ta.ws32 = d.ws32;
+    ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2; ta.lay_out_log2 = d.lay_log2;
     ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.k8 = 0;
     ta.c0 = d.c0; ta.k0tab = d.k0tab;
     ta.fint_w = resid ? nullptr : d.fint_w; ta.fint_out = d.scal;
@@ -81,9 +109,15 @@ __device__ __forceinline__ ThetaMixArgs theta_mix_args(const RhsDesc& d, bool re
     return ta;
 }
 
-template <int EPT, int RMAX, int SMAXF, int SMAXD, int STAGE>
-__global__ void __launch_bounds__(256) k_batch(const RhsDesc* __restrict__ descs, const int2* __restrict__ items,
-                                               int nitems, int* __restrict__ counter) {
+// NT: threads per tile.  WPE: waves per SIMD the register budget is sized for
+// (4: 128 registers, 2: 256), so that several tiles share a compute unit and
+// hide each other's memory and barrier latency.  args: the stage's argument array, one entry per
+// problem (LambdaArgs, ThetaArgs, MixLambdaArgs or ThetaMixArgs by stage).
+// REAL (theta stages): items are (problem, 2k + part), one real part of
+// wavenumber k per tile; otherwise (problem, k) on the complex line.
+template <int EPT, int RMAX, int SMAXF, int SMAXD, int STAGE, int NT, int WPE, bool REAL>
+__global__ void __launch_bounds__(NT, WPE) k_batch(const void* __restrict__ args, const int2* __restrict__ items,
+                                                    int nitems, int* __restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Cx<double> red[16];
     __shared__ double red2[2][16];
@@ -91,36 +125,36 @@ __global__ void __launch_bounds__(256) k_batch(const RhsDesc* __restrict__ descs
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = cur;
+        const int it = __builtin_amdgcn_readfirstlane(cur);
         __syncthreads();
         if (it >= nitems) break;          // every wave leaves once the list is exhausted
         const int2 w = items[it];
-        const RhsDesc& d = descs[w.x];
         if constexpr (STAGE == kBLamFwd) {
-            LambdaArgs<double> la = lam_args(d);
-            la.x = d.f; la.spec = d.spec64; la.rowscale = d.sin2;
-            la.w_mid = 1.0 / d.n; la.w_end = 1.0 / d.n;
-            lambda_fwd_body<double, EPT, RMAX>(la, w.y, smem_raw);
+            lambda_fwd_body<double, EPT, RMAX>(static_cast<const LambdaArgs<double>*>(args)[w.x], w.y, smem_raw);
         } else if constexpr (STAGE == kBTheta64) {
-            ThetaArgs<double> ta{};
-            ta.spec = d.spec64; ta.tw = d.p64m; ta.eq = d.eq64;
-            ta.n = d.n; ta.m = d.m; ta.N = d.N; ta.lay_log2 = d.lay_log2;
-            ta.fft = d.ft; ta.nthr_fft = d.theta_nthr_fft; ta.mode = kSolve; ta.k8 = 0;
-            ta.c0 = d.c0; ta.k0tab = d.k0tab; ta.fint_w = d.fint_w; ta.fint_out = d.scal;
-            theta_body<double, EPT, RMAX, SMAXD>(ta, w.y, smem_raw, red);
+            const ThetaArgs<double>& ta = static_cast<const ThetaArgs<double>*>(args)[w.x];
+            if constexpr (REAL)
+                theta_real_body<double, EPT, RMAX, SMAXD>(ta, w.y >> 1, w.y & 1, smem_raw, red);
+            else
+                theta_body<double, EPT, RMAX, SMAXD>(ta, w.y, smem_raw, red);
         } else if constexpr (STAGE == kBLamInv) {
-            LambdaArgs<double> la = lam_args(d);
-            la.y = d.u; la.spec = d.spec64; la.rowscale = nullptr;
-            la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0;
-            lambda_inv_body<double, EPT, RMAX>(la, w.y, smem_raw);
+            lambda_inv_body<double, EPT, RMAX>(static_cast<const LambdaArgs<double>*>(args)[w.x], w.y, smem_raw);
         } else if constexpr (STAGE == kBThetaFirst) {
-            theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, false, false>(theta_mix_args(d, false), w.y, smem_raw, red);
+            const ThetaMixArgs& ta = static_cast<const ThetaMixArgs*>(args)[w.x];
+            if constexpr (REAL)
+                theta_mixed_real_body<EPT, RMAX, SMAXF, SMAXD, false, false>(ta, w.y >> 1, w.y & 1, smem_raw, red);
+            else
+                theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, false, false>(ta, w.y, smem_raw, red);
         } else if constexpr (STAGE == kBLamMix) {
-            lambda_mix_body<EPT, RMAX>(mix_args(d), w.y, smem_raw);
+            lambda_mix_body<EPT, RMAX>(static_cast<const MixLambdaArgs*>(args)[w.x], w.y, smem_raw);
         } else if constexpr (STAGE == kBThetaResid) {
-            theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, true, false>(theta_mix_args(d, true), w.y, smem_raw, red);
+            const ThetaMixArgs& ta = static_cast<const ThetaMixArgs*>(args)[w.x];
+            if constexpr (REAL)
+                theta_mixed_real_body<EPT, RMAX, SMAXF, SMAXD, true, false>(ta, w.y >> 1, w.y & 1, smem_raw, red);
+            else
+                theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, true, false>(ta, w.y, smem_raw, red);
         } else {
-            lambda_update_body<EPT, RMAX>(mix_args(d), w.y, smem_raw, red2);
+            lambda_update_body<EPT, RMAX>(static_cast<const MixLambdaArgs*>(args)[w.x], w.y, smem_raw, red2);
         }
     }
 }

@@ -202,6 +202,39 @@ __device__ __forceinline__ void dft_odd(Cx<T>* v) {
     }
 }
 
+// The same odd-R transform with each output pair written to out[r * stride]
+// as soon as it is formed, and the pair sums and differences built in place
+// of the inputs: only the R inputs are held, not the inputs and the outputs
+// (radix 31 in float64 would need about 250 registers otherwise).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_odd_store(Cx<T>* v, Cx<T>* __restrict__ out, int stride) {
+    constexpr int H = (R - 1) / 2;
+    constexpr ct::Roots<R> W{};
+    const Cx<T> x0 = v[0];
+    Cx<T> sum = x0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        const Cx<T> a = v[j], b = v[R - j];
+        v[j] = a + b;
+        v[R - j] = a - b;
+        sum = sum + v[j];
+    }
+    out[0] = sum;
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+        Cx<T> A = x0, B{(T)0, (T)0};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int t = (r * j) % R;
+            A = A + v[j] * (T)W.c[t];
+            B = B + v[R - j] * (T)W.s[t];
+        }
+        const Cx<T> iB = mul_i(B);
+        out[r * stride] = INV ? A + iB : A - iB;
+        out[(R - r) * stride] = INV ? A - iB : A + iB;
+    }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft(Cx<T>* v) {
     if constexpr (R == 2) {
@@ -276,10 +309,14 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
                         v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
                     }
                 }
-                dft<T, R, INV>(v[b]);
                 const int base = (j - k) * R + k;
+                if constexpr (R >= 11 && (R & 1)) {
+                    dft_odd_store<T, R, INV>(v[b], buf + base, Ns);
+                } else {
+                    dft<T, R, INV>(v[b]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
+                    for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
+                }
             }
         }
     }

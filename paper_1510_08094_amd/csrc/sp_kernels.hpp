@@ -4,10 +4,11 @@
 //
 // Spectrum layout in HBM ("j-blocked"): the half spectrum X_k(theta_j),
 // k = 0..N (N = n/2), is stored as spec[((j / RL) * (N + 1) + k) * RL + j % RL]
-// with RL = 2^lay a power of two, the run length.  A theta workgroup reads
-// runs of RL consecutive rows of one wavenumber (a 128-byte line for RL = 8 in
-// float64); a lambda workgroup owns RW <= RL rows and writes its part of
-// every run.
+// with RL = 2^lay a power of two, the run length.  Each buffer takes the
+// layout its reader prefers: spectra read by a theta pass use runs of 8 rows
+// (one 128-byte line of a wavenumber in float64; a lambda workgroup owns
+// RW <= RL rows and writes its part of every run), spectra read by a lambda
+// pass use RL = RW (one contiguous block per lambda workgroup).
 #pragma once
 #include "sp_fft.hpp"
 
@@ -31,7 +32,7 @@ struct LambdaArgs {
     const Cx<T>* ptw;       // per-pass twiddles of the length-N complex DFT
     const double* rowscale; // per-row multiplier or nullptr
     int n, m, N, rw_log2;   // rw_log2: rows per workgroup (log2)
-    int lay_log2;           // spectrum run length (log2), >= rw_log2
+    int lay_log2;           // run length (log2) of the spectrum written (forward) or read (inverse)
     T w_mid, w_end;         // forward: output weight for 0<k<N and for k in {0,N}; inverse: input weights
     double out_scale;       // inverse: multiplier of the written rows
     FftDesc fft;
@@ -208,7 +209,9 @@ struct MixLambdaArgs {
     const Cx<double>* ptw64;   // per-pass twiddles of the length-N DFT (float64)
     double* partial;           // per block: sum of correction^2 and of u^2 (or nullptr)
     const double* rowscale;    // update: per-row output multiplier (or nullptr)
-    int n, m, N, rw_log2, lay_log2;
+    int n, m, N, rw_log2;
+    int lay_log2;              // run length (log2) of the float32 spectra read
+    int lay_out_log2;          // run length (log2) of the float64 spectrum written (mix)
     float in_w_mid, in_w_end;  // weights of the float32 spectra read by the inverse DFTs
     double mid_scale;          // mix: multiplier of the float32 inverse DFT before the float64 forward DFT
     double out_w_mid, out_w_end; // mix: weights of the float64 spectrum written
@@ -259,14 +262,14 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
     }
     __syncthreads();
     fft_lds<double, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw64, t, a.nthr, active);
-    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.lay_log2, a.m, jb, a.out_w_mid,
+    r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.lay_out_log2, a.m, jb, a.out_w_mid,
                                     a.out_w_end);
 }
 
 template <int EPT, int RMAX>
 __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    const int jb = lambda_tile(a.lay_out_log2 - a.rw_log2);
     if (jb << a.rw_log2 >= a.m) return;
     lambda_mix_body<EPT, RMAX>(a, jb, smem_raw);
 }
@@ -377,7 +380,10 @@ struct ThetaArgs {
     const Cx<T>* tw;        // per-pass twiddles of the length-m complex DFT
     const Cx<T>* eq;        // e^{-i pi q/(2m)}, q = 0..m-1
     const Cx<T>* ws;        // real-part pass: e^{-2 pi i q/m}, q = 0..m/4
-    int n, m, N, lay_log2;  // lay_log2: spectrum run length (log2)
+    Cx<T>* spec_out;        // spectrum written (may be spec when both layouts agree)
+    int n, m, N;
+    int lay_log2;           // run length (log2) of the spectrum read
+    int lay_out_log2;       // run length (log2) of the spectrum written
     FftDesc fft;
     int nthr_fft;
     int mode;               // ThetaMode
@@ -848,7 +854,7 @@ template <typename T, int EPT, int RMAX, int SMAX>
 __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigned char* smem_raw,
                                            Cx<double>* red) {
     Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem_raw);
-    const int m = a.m, N = a.N, lay = a.lay_log2;
+    const int m = a.m, N = a.N, lay = a.lay_log2, lay_out = a.lay_out_log2;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
     const T invm = (T)1 / (T)m;
@@ -911,11 +917,11 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
     __syncthreads();
     fft_lds<T, true, EPT, RMAX>(buf, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
     for (int j = tid; j < m; j += nthr) {
-        const size_t idx = spec_at(j, k, N, lay);
+        const size_t idx = spec_at(j, k, N, lay_out);
         const int pos = (j & 1) ? m - ((j + 1) >> 1) : (j >> 1);
         Cx<T> x = buf[pos] * invm;
         if (sine && (j & 1)) x = Cx<T>{-x.x, -x.y};
-        a.spec[idx] = x;
+        a.spec_out[idx] = x;
     }
 }
 
@@ -960,7 +966,9 @@ struct ThetaMixArgs {
     const Cx<float>* eq32;
     const Cx<double>* ws64;    // real-part pass: e^{-2 pi i q/m}, q = 0..m/4
     const Cx<float>* ws32;
-    int n, m, N, lay_log2;
+    int n, m, N;
+    int lay_log2;              // run length (log2) of sa / su
+    int lay_out_log2;          // run length (log2) of out
     FftDesc fft;
     int nthr_fft;
     int k8;
@@ -1156,7 +1164,7 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
     for (int j = tid; j < m; j += nthr) {
         Cx<float> x = buff[posj(j)] * finvm;
         if (sine && (j & 1)) x = Cx<float>{-x.x, -x.y};
-        a.out[idx(j)] = x;
+        a.out[spec_at(j, k, N, a.lay_out_log2)] = x;
     }
 }
 

@@ -199,7 +199,7 @@ __device__ __forceinline__ void theta_real_body(const ThetaArgs<T>& a, int k, in
     }
     rdct_split_inverse<T>(y, a.eq, a.ws, m, scale ? (T)m : (T)1, scale ? (T)m * (T)0.5 : (T)1, tid, nthr);
     fft_lds<T, true, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
-    store_part<T, T>(y, a.spec, part, k, m, N, a.lay_log2, sine, invm, tid, nthr);
+    store_part<T, T>(y, a.spec_out, part, k, m, N, a.lay_out_log2, sine, invm, tid, nthr);
 }
 
 template <typename T, int EPT, int RMAX, int SMAX>
@@ -345,7 +345,7 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
     const float fm = (float)m;
     rdct_split_inverse<float>(yf, a.eq32, a.ws32, m, TRANS ? 1.0f : fm, TRANS ? 1.0f : 0.5f * fm, tid, nthr);
     fft_lds<float, true, EPT, RMAX>(zf, 0, a.fft, a.tw32, tid, a.nthr_fft, tid < a.nthr_fft);
-    store_part<float, float>(yf, a.out, part, k, m, N, a.lay_log2, sine, 1.0f / fm, tid, nthr);
+    store_part<float, float>(yf, a.out, part, k, m, N, a.lay_out_log2, sine, 1.0f / fm, tid, nthr);
 }
 
 template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>

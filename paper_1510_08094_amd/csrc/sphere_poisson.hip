@@ -260,7 +260,7 @@ struct sp_plan_s {
     double* scal = nullptr;   // device scalars: [0] = integral of f, [1..2] = sum d^2, sum u^2
     size_t spec_elems = 0;
     // MIXED workspace
-    Cx<double>* specB = nullptr;   // float64 spectrum of the current iterate
+    Cx<double>* specB = nullptr;   // float64: theta output; mixed: spectrum of the current iterate
     Cx<float>* spec0 = nullptr;    // float32 spectrum of the first iterate
     Cx<float>* specd = nullptr;    // float32 spectrum of the correction
     double* partial = nullptr;     // per lambda block: sum d^2, sum u^2
@@ -334,8 +334,10 @@ Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
     L.off_k0 = take((size_t)2 * (m + 2) * sizeof(double));
     L.off_fint = take((size_t)m * sizeof(double));
     L.off_scal = take(16 * sizeof(double));
+    // second float64 spectrum: the theta output of the float64 path (lambda
+    // read layout), and in mixed plans the spectrum of the current iterate
+    L.off_specB = take(L.spec_elems * sizeof(Cx<double>));
     if (mixed) {
-        L.off_specB = take(L.spec_elems * sizeof(Cx<double>));
         L.off_spec0 = take(L.spec_elems * sizeof(Cx<float>));
         L.off_specd = take(L.spec_elems * sizeof(Cx<float>));
         L.off_partial = take(2 * nblk * sizeof(double));
@@ -602,8 +604,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     p->k0tab = (double*)(b + L.off_k0);
     p->fint_w = (double*)(b + L.off_fint);
     p->scal = (double*)(b + L.off_scal);
+    p->specB = (Cx<double>*)(b + L.off_specB);
     if (mixed) {
-        p->specB = (Cx<double>*)(b + L.off_specB);
         p->spec0 = (Cx<float>*)(b + L.off_spec0);
         p->specd = (Cx<float>*)(b + L.off_specd);
         p->partial = (double*)(b + L.off_partial);
@@ -1039,7 +1041,8 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     ta.tw = p->t64.pass_m;
     ta.eq = p->t64.eq;
     ta.ws = p->t64.ws;
-    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2;
+    ta.spec_out = p->specB;
+    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2; ta.lay_out_log2 = p->rw_log2;
     ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads;
     ta.mode = mode;
@@ -1053,7 +1056,9 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
         hipLaunchKernelGGL(p->theta_real ? p->kd.theta_real : p->kd.theta, dim3(p->theta_grid),
                            dim3(p->theta_threads), p->theta_lds64, s, ta);
     }
-    // inverse lambda
+    // inverse lambda: reads the theta output, one contiguous block per workgroup
+    la.spec = p->specB;
+    la.lay_log2 = p->rw_log2;
     if (!adjoint_weights) { la.w_mid = 1.0; la.w_end = 1.0; la.out_scale = 1.0; la.rowscale = nullptr; }
     else { la.w_mid = 0.5; la.w_end = 1.0; la.out_scale = 1.0 / n; la.rowscale = p->sin2; }
     {
@@ -1114,7 +1119,10 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     ta.sa = p->spec64; ta.fco = p->fco; ta.su = p->specB; ta.out = p->spec0;
     ta.tw64 = p->t64.pass_m; ta.eq64 = p->t64.eq; ta.tw32 = p->t32.pass_m; ta.eq32 = p->t32.eq;
     ta.ws64 = p->t64.ws; ta.ws32 = p->t32.ws;
-    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2; ta.fft = p->fft_theta;
+    // the float32 spectra keep theta's run length: written by halves (one real
+    // part per workgroup), shorter runs fragment those writes more than they
+    // help the lambda reads
+    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2; ta.lay_out_log2 = p->lay_log2; ta.fft = p->fft_theta;
     ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
     ta.fint_w = p->fint_w; ta.fint_out = p->scal;
     ta.k64 = p->desc.low_k_fp64 < 0 ? std::max(16, m / 64) : std::max(1, p->desc.low_k_fp64);
@@ -1138,7 +1146,9 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
         ma.s0 = p->spec0; ma.sd = p->specd; ma.su = p->specB; ma.u = u;
         ma.tw32 = p->t32.tw_n; ma.tw64 = p->t64.tw_n; ma.partial = want ? p->partial : nullptr;
         ma.ptw32 = p->t32.pass_n; ma.ptw64 = p->t64.pass_n;
-        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2; ma.lay_log2 = p->lay_log2;
+        ma.n = n; ma.m = m; ma.N = N; ma.rw_log2 = p->rw_log2;
+        ma.lay_log2 = p->lay_log2;      // float32 spectra written by theta
+        ma.lay_out_log2 = p->lay_log2;  // float64 spectrum of the iterate, read by theta
         ma.fft = p->fft_lam; ma.nthr = p->lam_threads; ma.accumulate = 0;
         if (!adjoint) {
             ma.in_w_mid = 1.0f; ma.in_w_end = 1.0f; ma.mid_scale = 1.0;
@@ -1256,6 +1266,7 @@ struct SizeTables {              // tables shared by every problem with the same
     FftDesc desc{};
     size_t off64 = 0, off32 = 0, offp64 = 0, offp32 = 0;   // lambda: tw_n and pass tables
     size_t offeq64 = 0, offeq32 = 0, offsin2 = 0, offk0 = 0, offfint = 0;  // theta extras
+    size_t offws64 = 0, offws32 = 0;   // theta: real-part split twiddles
 };
 
 struct BatchPlan {
@@ -1279,32 +1290,62 @@ struct BatchPlan {
 std::mutex g_batch_mu;
 BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebuilt when it changes)
 
+// Builds of every stage (a problem's class per stage):
+//   0: radices up to 16, 256 threads, 128 registers (168 for the complex
+//      theta line, whose bodies hold two solves' state);
+//   1: radices up to 31, 256 threads, 256 registers;
+//   2, 3 (theta only): one real part per tile (even m), 128 threads, radices
+//      up to 16 in 128 registers or up to 31 in 256.
+// A problem runs in the small-radix build of a stage when the transform of
+// that stage's direction uses no radix above 16.
+constexpr int kBatchClasses = 4;
+constexpr int kBatchSmallRadix = 16;
+constexpr int kBatchRealThreads = 128;
+
 struct BatchKernels {
-    void (*st[sp::kBStages])(const sp::RhsDesc*, const int2*, int, int*);
+    void (*st[sp::kBStages][kBatchClasses])(const void*, const int2*, int, int*);
 };
+
+template <int STG>
+void batch_stage_kernels(BatchKernels& k) {
+    constexpr bool theta = STG == sp::kBTheta64 || STG == sp::kBThetaFirst || STG == sp::kBThetaResid;
+    k.st[STG][0] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxF, kSmaxD, STG, kBatchThreads, theta ? 3 : 4, false>;
+    k.st[STG][1] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, STG, kBatchThreads, 2, false>;
+    if constexpr (theta) {
+        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchRealThreads, 4, true>;
+        k.st[STG][3] = &sp::k_batch<kEPT, 32, kSmaxR, kSmaxR, STG, kBatchRealThreads, 2, true>;
+    } else {
+        k.st[STG][2] = k.st[STG][3] = nullptr;
+    }
+}
 
 BatchKernels batch_kernels() {
     BatchKernels k;
-    k.st[sp::kBLamFwd] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamFwd>;
-    k.st[sp::kBTheta64] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBTheta64>;
-    k.st[sp::kBLamInv] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamInv>;
-    k.st[sp::kBThetaFirst] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBThetaFirst>;
-    k.st[sp::kBLamMix] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamMix>;
-    k.st[sp::kBThetaResid] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBThetaResid>;
-    k.st[sp::kBLamUpd] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, sp::kBLamUpd>;
+    batch_stage_kernels<sp::kBLamFwd>(k);
+    batch_stage_kernels<sp::kBTheta64>(k);
+    batch_stage_kernels<sp::kBLamInv>(k);
+    batch_stage_kernels<sp::kBThetaFirst>(k);
+    batch_stage_kernels<sp::kBLamMix>(k);
+    batch_stage_kernels<sp::kBThetaResid>(k);
+    batch_stage_kernels<sp::kBLamUpd>(k);
     return k;
 }
 
-// per-problem launch parameters inside the fixed 256-thread batch tiles;
-// rl / rt: radix orders (empty: fixed rule)
+int radix_class(const std::vector<int>& rad) {
+    for (int r : rad)
+        if (r > kBatchSmallRadix) return 1;
+    return 0;
+}
+
+// per-problem launch parameters inside the batch tiles; rl / rt: radix
+// orders (empty: fixed rule).  Even m runs one real part per 128-thread theta
+// tile (DFT length m/2) when that tile holds it, otherwise the complex line
+// (DFT length m) in a 256-thread tile.
 bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, int* rwl, int* lam_nthr,
-                    int* th_fft) {
-    // the batch runs the complex-line theta pass: its DFT has length m
-    if (!valid_radices(rl, n / 2)) rl.clear();
-    if (!valid_radices(rt, m)) rt.clear();
-    if (rl.empty() && !factorize(n / 2, rl)) return false;
-    if (rt.empty() && !factorize(m, rt)) return false;
+                    int* th_fft, bool* th_real) {
     const int N = n / 2;
+    if (!valid_radices(rl, N)) rl.clear();
+    if (rl.empty() && !factorize(N, rl)) return false;
     const int t = fft_threads(rl, N);
     if (t > kBatchThreads) return false;
     int best = 0;
@@ -1316,6 +1357,23 @@ bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, in
     }
     *rwl = best;
     *lam_nthr = t;
+    *th_real = false;
+    if ((m & 1) == 0) {
+        std::vector<int> r = rt;
+        if (!valid_radices(r, m / 2)) r.clear();
+        if (!r.empty() || factorize(m / 2, r)) {
+            const int f = fft_threads(r, m / 2);
+            const int need = std::max(std::max(f, solve_threads(m, kSmaxR)), sp::real_theta_min_threads(m));
+            if (need <= kBatchRealThreads) {
+                rt = r;
+                *th_fft = f;
+                *th_real = true;
+                return true;
+            }
+        }
+    }
+    if (!valid_radices(rt, m)) rt.clear();
+    if (rt.empty() && !factorize(m, rt)) return false;
     *th_fft = fft_threads(rt, m);
     const int need = std::max(std::max(*th_fft, ceil_div(m, sp::kThetaHold)),
                               std::max(solve_threads(m, kSmaxD), solve_threads(m, kSmaxF)));
@@ -1354,16 +1412,19 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     }
     std::vector<int> rwl(count), lnt(count), tft(count);
     std::vector<std::vector<int>> rls(count), rts(count);
+    std::vector<char> treal(count);
     for (int r = 0; r < count; ++r) {
         Sched sc = cached_schedule(n[r], m[r], precision);
         rls[r] = sc.lam;
         rts[r] = sc.theta;
-        if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r])) {
+        bool re = false;
+        if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r], &re)) {
             rls[r].clear();
             rts[r].clear();
-            if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r]))
+            if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r], &re))
                 return SP_ERR_UNSUPPORTED_SIZE;
         }
+        treal[r] = re ? 1 : 0;
     }
 
     BatchPlan* bp = new (std::nothrow) BatchPlan();
@@ -1381,12 +1442,12 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     // tables per distinct n and m
     // tables per distinct (size, radix order)
     std::map<std::string, SizeTables> lam, th;
-    std::map<std::string, std::vector<Cx<double>>> lam_tw, lam_pass, th_pass, th_eq;
+    std::map<std::string, std::vector<Cx<double>>> lam_tw, lam_pass, th_pass, th_eq, th_ws;
     std::map<std::string, std::vector<double>> th_sin2, th_k0, th_fint;
     std::vector<std::string> lkey(count), tkey(count);
     for (int r = 0; r < count; ++r) {
         lkey[r] = std::to_string(n[r]) + "|" + radix_str(rls[r]);
-        tkey[r] = std::to_string(m[r]) + "|" + radix_str(rts[r]);
+        tkey[r] = std::to_string(m[r]) + (treal[r] ? "r|" : "c|") + radix_str(rts[r]);
     }
     for (int r = 0; r < count; ++r) {
         const std::string& lk = lkey[r];
@@ -1406,10 +1467,15 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         }
         if (!th.count(tk)) {
             SizeTables& t = th[tk];
-            t.len = m[r];
+            t.len = treal[r] ? m[r] / 2 : m[r];
             t.radices = rts[r];
             t.desc = make_desc(t.radices, t.len, &th_pass[tk]);
             host_theta_tables(m[r], th_eq[tk], th_sin2[tk], th_k0[tk], th_fint[tk]);
+            std::vector<Cx<double>>& ws = th_ws[tk];
+            ws.resize(m[r] / 4 + 1);
+            for (int q = 0; q <= m[r] / 4; ++q) cis_neg(q, m[r], &ws[q].x, &ws[q].y);
+            t.offws64 = take(ws.size() * sizeof(Cx<double>));
+            t.offws32 = take(ws.size() * sizeof(Cx<float>));
             t.offp64 = take(th_pass[tk].size() * sizeof(Cx<double>));
             t.offp32 = take(th_pass[tk].size() * sizeof(Cx<float>));
             t.offeq64 = take(m[r] * sizeof(Cx<double>));
@@ -1422,7 +1488,6 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     // per-problem workspace
     std::vector<size_t> o64(count), oB(count), o0(count), od(count), opart(count), ofco(count);
     std::vector<int> nblk(count);
-    size_t lam_lds = 0, th_lds = 0;
     for (int r = 0; r < count; ++r) {
         const int rw = 1 << rwl[r];
         nblk[r] = (m[r] + rw - 1) / rw;
@@ -1435,24 +1500,47 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             opart[r] = take(2 * (size_t)nblk[r] * sizeof(double));
             ofco[r] = take((size_t)(n[r] / 2 + 1) * sp::solve_slot_stride(m[r]) * sizeof(Cx<double>));
         }
-        lam_lds = std::max(lam_lds, (size_t)rw * (n[r] / 2) * sizeof(Cx<double>));
-        th_lds = std::max(th_lds, theta_lds_bytes<double>(m[r], std::max(solve_threads(m[r], kSmaxD),
-                                                                            solve_threads(m[r], kSmaxF))));
     }
-    // work lists: (rhs, tile) sorted by decreasing tile cost
-    std::vector<int2> lam_items, th_items;
+    // work lists per kernel build: (rhs, tile) sorted by decreasing tile cost
+    std::vector<int2> lam_items[kBatchClasses], th_items[kBatchClasses];
+    size_t lam_lds_c[kBatchClasses] = {}, th_lds_c[kBatchClasses] = {};
     for (int r = 0; r < count; ++r) {
-        for (int jb = 0; jb < nblk[r]; ++jb) lam_items.push_back(make_int2(r, jb));
-        for (int k = 0; k <= n[r] / 2; ++k) th_items.push_back(make_int2(r, k));
+        const int lc = radix_class(rls[r]), tc = radix_class(rts[r]) + (treal[r] ? 2 : 0);
+        for (int jb = 0; jb < nblk[r]; ++jb) lam_items[lc].push_back(make_int2(r, jb));
+        for (int k = 0; k <= n[r] / 2; ++k) {
+            if (treal[r]) {
+                th_items[tc].push_back(make_int2(r, 2 * k));
+                th_items[tc].push_back(make_int2(r, 2 * k + 1));
+            } else {
+                th_items[tc].push_back(make_int2(r, k));
+            }
+        }
+        lam_lds_c[lc] = std::max(lam_lds_c[lc], ((size_t)n[r] / 2 << rwl[r]) * sizeof(Cx<double>));
+        const size_t tl = treal[r] ? real_theta_lds_bytes(m[r], solve_threads(m[r], kSmaxR))
+                                   : theta_lds_bytes<double>(m[r], std::max(solve_threads(m[r], kSmaxD),
+                                                                            solve_threads(m[r], kSmaxF)));
+        th_lds_c[tc] = std::max(th_lds_c[tc], tl);
     }
-    std::stable_sort(lam_items.begin(), lam_items.end(), [&](int2 x, int2 y) {
-        return (long long)n[x.x] << rwl[x.x] > (long long)n[y.x] << rwl[y.x];
-    });
-    std::stable_sort(th_items.begin(), th_items.end(), [&](int2 x, int2 y) { return m[x.x] > m[y.x]; });
+    for (int c = 0; c < kBatchClasses; ++c) {
+        std::stable_sort(lam_items[c].begin(), lam_items[c].end(), [&](int2 x, int2 y) {
+            return (long long)n[x.x] << rwl[x.x] > (long long)n[y.x] << rwl[y.x];
+        });
+        std::stable_sort(th_items[c].begin(), th_items[c].end(), [&](int2 x, int2 y) { return m[x.x] > m[y.x]; });
+    }
     const size_t o_desc = take(count * sizeof(sp::RhsDesc));
-    const size_t o_lam_items = take(lam_items.size() * sizeof(int2));
-    const size_t o_th_items = take(th_items.size() * sizeof(int2));
-    const size_t o_ctr = take(sp::kBStages * sizeof(int));
+    // per-stage argument arrays, one entry per problem
+    const size_t o_lfwd = take(count * sizeof(sp::LambdaArgs<double>));
+    const size_t o_linv = mixed ? 0 : take(count * sizeof(sp::LambdaArgs<double>));
+    const size_t o_th64 = mixed ? 0 : take(count * sizeof(sp::ThetaArgs<double>));
+    const size_t o_thf = mixed ? take(count * sizeof(sp::ThetaMixArgs)) : 0;
+    const size_t o_thr = mixed ? take(count * sizeof(sp::ThetaMixArgs)) : 0;
+    const size_t o_mix = mixed ? take(count * sizeof(sp::MixLambdaArgs)) : 0;
+    size_t o_lam_items[kBatchClasses], o_th_items[kBatchClasses];
+    for (int c = 0; c < kBatchClasses; ++c) {
+        o_lam_items[c] = take(lam_items[c].size() * sizeof(int2));
+        o_th_items[c] = take(th_items[c].size() * sizeof(int2));
+    }
+    const size_t o_ctr = take(sp::kBStages * kBatchClasses * sizeof(int));
     const size_t o_scal = take(4 * (size_t)count * sizeof(double));
     const size_t o_nblk = take(count * sizeof(int));
 
@@ -1470,7 +1558,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         const SizeTables& T = th[tkey[r]];
         sp::RhsDesc& d = descs[r];
         d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r]; d.lay_log2 = rwl[r];
-        d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r];
+        d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r]; d.theta_real = treal[r];
         d.k64 = std::max(16, m[r] / 64);
         d.c0 = 0.0;
         d.fl = L.desc; d.ft = T.desc;
@@ -1489,6 +1577,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         d.p32m = (const Cx<float>*)(B + T.offp32);
         d.eq64 = (const Cx<double>*)(B + T.offeq64);
         d.eq32 = (const Cx<float>*)(B + T.offeq32);
+        d.ws64 = (const Cx<double>*)(B + T.offws64);
+        d.ws32 = (const Cx<float>*)(B + T.offws32);
         d.sin2 = (const double*)(B + T.offsin2);
         d.k0tab = (const double*)(B + T.offk0);
         d.fint_w = (const double*)(B + T.offfint);
@@ -1524,10 +1614,38 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         stage(kv.second.offsin2, th_sin2[mm].data(), th_sin2[mm].size() * sizeof(double));
         stage(kv.second.offk0, th_k0[mm].data(), th_k0[mm].size() * sizeof(double));
         stage(kv.second.offfint, th_fint[mm].data(), th_fint[mm].size() * sizeof(double));
+        auto w32 = to32(th_ws[mm]);
+        stage(kv.second.offws64, th_ws[mm].data(), th_ws[mm].size() * sizeof(Cx<double>));
+        stage(kv.second.offws32, w32.data(), w32.size() * sizeof(Cx<float>));
     }
     stage(o_desc, descs.data(), descs.size() * sizeof(sp::RhsDesc));
-    stage(o_lam_items, lam_items.data(), lam_items.size() * sizeof(int2));
-    stage(o_th_items, th_items.data(), th_items.size() * sizeof(int2));
+    {
+        std::vector<sp::LambdaArgs<double>> lf(count), li(count);
+        std::vector<sp::ThetaArgs<double>> t64(count);
+        std::vector<sp::ThetaMixArgs> tf(count), tr(count);
+        std::vector<sp::MixLambdaArgs> mx(count);
+        for (int r = 0; r < count; ++r) {
+            lf[r] = sp::batch_lambda_args(descs[r], true);
+            li[r] = sp::batch_lambda_args(descs[r], false);
+            t64[r] = sp::batch_theta_args(descs[r]);
+            tf[r] = sp::batch_theta_mix_args(descs[r], false);
+            tr[r] = sp::batch_theta_mix_args(descs[r], true);
+            mx[r] = sp::batch_mix_args(descs[r]);
+        }
+        stage(o_lfwd, lf.data(), count * sizeof(lf[0]));
+        if (mixed) {
+            stage(o_thf, tf.data(), count * sizeof(tf[0]));
+            stage(o_thr, tr.data(), count * sizeof(tr[0]));
+            stage(o_mix, mx.data(), count * sizeof(mx[0]));
+        } else {
+            stage(o_linv, li.data(), count * sizeof(li[0]));
+            stage(o_th64, t64.data(), count * sizeof(t64[0]));
+        }
+    }
+    for (int c = 0; c < kBatchClasses; ++c) {
+        stage(o_lam_items[c], lam_items[c].data(), lam_items[c].size() * sizeof(int2));
+        stage(o_th_items[c], th_items[c].data(), th_items[c].size() * sizeof(int2));
+    }
     stage(o_nblk, nblk.data(), nblk.size() * sizeof(int));
     for (auto& up : uploads) {
         e = hipMemcpy(B + up.first, up.second.data(), up.second.size(), hipMemcpyHostToDevice);
@@ -1541,34 +1659,43 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
                                     : std::vector<int>{sp::kBLamFwd, sp::kBTheta64, sp::kBLamInv};
     e = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamCreate"); }
-    std::vector<int> grids(sp::kBStages, 0);
-    std::vector<size_t> ldss(sp::kBStages, 0);
+    // each (stage, build) with work: its LDS, occupancy and persistent grid
+    struct Launch { void (*fn)(const void*, const int2*, int, int*); int grid, nt; size_t lds, items, args; int nit, ctr; };
+    std::vector<Launch> launches;
     for (int stg : stages) {
         const bool is_theta = stg == sp::kBTheta64 || stg == sp::kBThetaFirst || stg == sp::kBThetaResid;
-        const size_t lds = is_theta ? th_lds : lam_lds;
-        if (lds + 1024 > lds_limit) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
-        (void)hipFuncSetAttribute((const void*)K.st[stg], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)K.st[stg], kBatchThreads, lds) !=
-                hipSuccess || occ < 1)
-            occ = 1;
-        const int nit = is_theta ? (int)th_items.size() : (int)lam_items.size();
-        grids[stg] = std::max(1, std::min(nit, prop.multiProcessorCount * occ));
-        ldss[stg] = lds;
+        for (int c = 0; c < kBatchClasses; ++c) {
+            const int nit = (int)(is_theta ? th_items[c].size() : lam_items[c].size());
+            if (nit == 0) continue;
+            const size_t lds = is_theta ? th_lds_c[c] : lam_lds_c[c];
+            if (lds + 1024 > lds_limit) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
+            Launch L;
+            L.fn = K.st[stg][c];
+            L.nt = c >= 2 ? kBatchRealThreads : kBatchThreads;
+            (void)hipFuncSetAttribute((const void*)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)L.fn, L.nt, lds) !=
+                    hipSuccess || occ < 1)
+                occ = 1;
+            L.grid = std::max(1, std::min(nit, prop.multiProcessorCount * occ));
+            L.lds = lds;
+            L.items = is_theta ? o_th_items[c] : o_lam_items[c];
+            L.nit = nit;
+            L.ctr = stg * kBatchClasses + c;
+            L.args = stg == sp::kBLamFwd ? o_lfwd : stg == sp::kBTheta64 ? o_th64 : stg == sp::kBLamInv ? o_linv
+                   : stg == sp::kBThetaFirst ? o_thf : stg == sp::kBThetaResid ? o_thr : o_mix;
+            launches.push_back(L);
+        }
     }
     (void)hipGetLastError();
     e = hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamBeginCapture"); }
     int* ctr = (int*)(B + o_ctr);
     const sp::RhsDesc* dd = (const sp::RhsDesc*)(B + o_desc);
-    hipLaunchKernelGGL(sp::k_batch_reset, dim3(1), dim3(64), 0, bp->cap, ctr, (int)sp::kBStages);
-    for (int stg : stages) {
-        const bool is_theta = stg == sp::kBTheta64 || stg == sp::kBThetaFirst || stg == sp::kBThetaResid;
-        const int2* items = (const int2*)(B + (is_theta ? o_th_items : o_lam_items));
-        const int nit = is_theta ? (int)th_items.size() : (int)lam_items.size();
-        hipLaunchKernelGGL(K.st[stg], dim3(grids[stg]), dim3(kBatchThreads), ldss[stg], bp->cap, dd, items, nit,
-                           ctr + stg);
-    }
+    hipLaunchKernelGGL(sp::k_batch_reset, dim3(1), dim3(64), 0, bp->cap, ctr, (int)(sp::kBStages * kBatchClasses));
+    for (const Launch& L : launches)
+        hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(L.nt), L.lds, bp->cap, (const void*)(B + L.args),
+                           (const int2*)(B + L.items), L.nit, ctr + L.ctr);
     if (mixed) hipLaunchKernelGGL(sp::k_batch_norms, dim3(count), dim3(256), 0, bp->cap, dd, (const int*)(B + o_nblk));
     e = hipStreamEndCapture(bp->cap, &bp->graph);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamEndCapture"); }

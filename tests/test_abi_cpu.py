@@ -68,8 +68,10 @@ def test_workspace_bytes_scale(lib):
     small = lib.sphere_poisson_workspace_bytes(ctypes.byref(_desc(64, 64)))
     big = lib.sphere_poisson_workspace_bytes(ctypes.byref(_desc(1024, 1024)))
     assert 0 < small < big
-    # spectrum is (n/2+1) x m complex float64, about 8 bytes per sample
-    assert 8 * 1024 * 1024 <= big < 16 * 1024 * 1024
+    # two float64 spectra ((n/2+1) x m complex each: the theta input in runs for
+    # the theta pass, its output in runs for the lambda pass), about 16 bytes
+    # per sample, plus small tables
+    assert 16 * 1024 * 1024 <= big < 20 * 1024 * 1024
     assert lib.sphere_poisson_workspace_bytes(ctypes.byref(_desc(63, 64))) == 0
 
 
