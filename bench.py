@@ -40,12 +40,16 @@ def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
     grid = m * n * 8
     table = {
         "lambda_fwd": grid + spec64,
-        # mixed first solve: reads sin^2 b, writes F in place and the float32 solution spectrum
+        # mixed first solve: reads the spectrum of sin^2 f, writes its theta coefficients F and
+        # the float32 solution spectrum
         "theta": 2 * spec64 if precision == "fp64" else 2 * spec64 + spec32,
         "lambda_inv": spec64 + grid,
-        "lambda_mix": spec32 + spec64,
+        # mix: reads the float32 first solution, writes its float64 spectrum and
+        # keeps the float32 rows (4 B per sample) in u for the update
+        "lambda_mix": spec32 + spec64 + grid // 2,
         "theta_resid": 2 * spec64 + spec32,
-        "lambda_upd": 2 * spec32 + grid,
+        # update: reads the kept float32 rows and the correction spectrum, writes u
+        "lambda_upd": grid // 2 + spec32 + grid,
     }
     return table[kind]
 

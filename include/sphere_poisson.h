@@ -115,6 +115,9 @@ int sphere_poisson_plan(sp_plan* out, const sp_desc* desc, void* hip_stream);
  * f is not required to have zero mean (the paper's precondition); the
  * bordered k = 0 system is solved as is and info->f_integral reports the
  * mean.  `info` may be NULL; it is filled only with SP_SYNC_INFO.
+ * MIXED plans also use u as scratch between their kernels (the float32 first
+ * iterate is kept there until the update pass overwrites it), so u holds the
+ * solution only once the stream reaches the end of the solve.
  * Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG, SP_ERR_ALIAS, SP_ERR_HIP,
  * SP_ERR_NOT_CONVERGED (MIXED, SP_SYNC_INFO and tol > 0 only). */
 int sphere_poisson_solve(sp_plan plan, const double* f, double* u, double integral,
@@ -158,9 +161,9 @@ typedef enum {
     SP_KERNEL_LAMBDA_FWD = 0,   /* lambda real DFT of a block of rows (writes the half spectrum) */
     SP_KERNEL_THETA = 1,        /* per-wavenumber theta transform + banded solve + inverse */
     SP_KERNEL_LAMBDA_INV = 2,   /* inverse lambda real DFT of a block of rows */
-    SP_KERNEL_LAMBDA_MIX = 3,   /* MIXED: float32 inverse + float64 forward lambda DFT of the first iterate */
+    SP_KERNEL_LAMBDA_MIX = 3,   /* MIXED: float32 inverse + float64 forward lambda DFT of the first iterate (kept in u) */
     SP_KERNEL_THETA_RESID = 4,  /* MIXED: float64 residual in coefficient space + float32 correction solve */
-    SP_KERNEL_LAMBDA_UPD = 5,   /* MIXED: float32 inverse lambda DFTs + float64 update of u */
+    SP_KERNEL_LAMBDA_UPD = 5,   /* MIXED: float32 inverse lambda DFT of the correction + float64 update of u */
     SP_KERNEL_REDUCE = 6,       /* norms for the convergence report */
     SP_KERNEL_KINDS = 7
 } sp_kernel_kind;

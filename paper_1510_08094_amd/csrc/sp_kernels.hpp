@@ -231,6 +231,9 @@ struct LineHold {
 // float64 forward DFT of u0 with weights out_w -> su.  Forward solve: weights
 // 1, mid_scale 1, out_w 1/n.  Adjoint: in_w (1/2, 1), mid_scale 1/n, out_w
 // (2, 1) (the transposes of the real DFT pair).  LDS per row: N float64 complex.
+// The float32 inverse DFT itself (before mid_scale) is also kept, as n floats
+// at the start of the row's own output row u[j], for the update pass: it reads
+// 4 bytes per sample there instead of transforming s0 a second time.
 template <int EPT, int RMAX>
 __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw) {
     Cx<double>* lines = reinterpret_cast<Cx<double>*>(smem_raw);
@@ -252,6 +255,14 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
     for (int e = 0; e < H; ++e) {
         const int i = t + e * a.nthr;
         if (active && i < N) hold[e] = fbuf[i];
+    }
+    if (active) {
+        Cx<float>* keep = reinterpret_cast<Cx<float>*>(a.u + (size_t)j * a.n);
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            const int i = t + e * a.nthr;
+            if (i < N) keep[i] = hold[e];
+        }
     }
     __syncthreads();
     Cx<double>* dbuf = lines + (size_t)line * N;
@@ -275,7 +286,9 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
 }
 
 // u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
-// weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].
+// weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].  u0 is
+// the copy the mix pass left at the start of each output row (every row is
+// read into LDS before any of the tile's rows is overwritten).
 // Optionally accumulates per-block sums of (s d)^2 and u^2.
 template <int EPT, int RMAX>
 __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw,
@@ -287,15 +300,15 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     const size_t stride = 2 * (size_t)N;
-    if (!a.accumulate)
-        c2r_load_prepare<float, float>(fl, stride, a.s0, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
-                                       a.in_w_end);
+    Cx<float>* b0 = fl + (size_t)line * stride;
+    Cx<float>* b1 = b0 + N;
+    if (!a.accumulate && active) {
+        const Cx<float>* keep = reinterpret_cast<const Cx<float>*>(a.u + (size_t)j * a.n);
+        for (int i = t; i < N; i += a.nthr) b0[i] = keep[i];
+    }
     c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
                                    a.in_w_end);
     __syncthreads();
-    Cx<float>* b0 = fl + (size_t)line * stride;
-    Cx<float>* b1 = b0 + N;
-    if (!a.accumulate) fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N, a.fft, a.ptw32, t, a.nthr, active);
     fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N + N, a.fft, a.ptw32, t, a.nthr, active);
     double sd2 = 0.0, su2 = 0.0;
     if (active) {

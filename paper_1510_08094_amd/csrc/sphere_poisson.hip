@@ -1295,7 +1295,7 @@ BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebui
 //      theta line, whose bodies hold two solves' state);
 //   1: radices up to 31, 256 threads, 256 registers;
 //   2, 3 (theta only): one real part per tile (even m), 128 threads, radices
-//      up to 16 in 128 registers or up to 31 in 256.
+//      up to 16 in 168 registers or up to 31 in 256.
 // A problem runs in the small-radix build of a stage when the transform of
 // that stage's direction uses no radix above 16.
 constexpr int kBatchClasses = 4;
@@ -1312,7 +1312,7 @@ void batch_stage_kernels(BatchKernels& k) {
     k.st[STG][0] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxF, kSmaxD, STG, kBatchThreads, theta ? 3 : 4, false>;
     k.st[STG][1] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, STG, kBatchThreads, 2, false>;
     if constexpr (theta) {
-        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchRealThreads, 4, true>;
+        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchRealThreads, 3, true>;
         k.st[STG][3] = &sp::k_batch<kEPT, 32, kSmaxR, kSmaxR, STG, kBatchRealThreads, 2, true>;
     } else {
         k.st[STG][2] = k.st[STG][3] = nullptr;
