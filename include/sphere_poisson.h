@@ -95,7 +95,7 @@ typedef struct sp_plan_s* sp_plan;
 /* Create a plan for one (n, m, precision).  Validates sizes, factorises n/2
  * and m into radices <= 31, computes float64 twiddle tables on the host
  * (exact-angle reduction) and uploads them, allocates the spectrum workspace
- * (about 8 bytes per grid point for SP_FP64, 24 for SP_MIXED) and picks the
+ * (about 16 bytes per grid point for SP_FP64, 32 for SP_MIXED) and picks the
  * launch schedule.  `hip_stream` is used for the uploads.
  * Schedules: the radix order of the lambda and theta transforms and the rows
  * per lambda tile come from the autotuner cache when it has an entry for the
