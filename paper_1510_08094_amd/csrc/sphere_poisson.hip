@@ -1294,13 +1294,20 @@ BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebui
 //   0: radices up to 16, 256 threads, 128 registers (168 for the complex
 //      theta line, whose bodies hold two solves' state);
 //   1: radices up to 31, 256 threads, 256 registers;
-//   2, 3 (theta only): one real part per tile (even m), 128 threads, radices
-//      up to 16 in 168 registers or up to 31 in 256.
+//   2, 3 (theta only): one real part per tile (even m), 128 threads and
+//      chunks of up to 17 rows, radices up to 16 in 168 registers or up to 31
+//      in 256;
+//   4, 5 (theta only): the same in one wave (64 threads, chunks of up to 21
+//      rows) for the lines that fit it (m up to 1344).
 // A problem runs in the small-radix build of a stage when the transform of
-// that stage's direction uses no radix above 16.
-constexpr int kBatchClasses = 4;
+// that stage's direction uses no radix above 16.  Small tiles keep more
+// wavenumbers in flight per compute unit; a line of m <= 2048 gives few
+// threads work in any phase.
+constexpr int kBatchClasses = 6;
 constexpr int kBatchSmallRadix = 16;
 constexpr int kBatchRealThreads = 128;
+constexpr int kBatchSmaxR = 17;    // chunk rows per thread in those tiles: the shortest that lets m = 2048 fit
+constexpr int kBatchWaveThreads = 64;
 
 struct BatchKernels {
     void (*st[sp::kBStages][kBatchClasses])(const void*, const int2*, int, int*);
@@ -1312,10 +1319,12 @@ void batch_stage_kernels(BatchKernels& k) {
     k.st[STG][0] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxF, kSmaxD, STG, kBatchThreads, theta ? 3 : 4, false>;
     k.st[STG][1] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, STG, kBatchThreads, 2, false>;
     if constexpr (theta) {
-        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchRealThreads, 3, true>;
-        k.st[STG][3] = &sp::k_batch<kEPT, 32, kSmaxR, kSmaxR, STG, kBatchRealThreads, 2, true>;
+        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kBatchSmaxR, kBatchSmaxR, STG, kBatchRealThreads, 3, true>;
+        k.st[STG][3] = &sp::k_batch<kEPT, 32, kBatchSmaxR, kBatchSmaxR, STG, kBatchRealThreads, 2, true>;
+        k.st[STG][4] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchWaveThreads, 3, true>;
+        k.st[STG][5] = &sp::k_batch<kEPT, 32, kSmaxR, kSmaxR, STG, kBatchWaveThreads, 2, true>;
     } else {
-        k.st[STG][2] = k.st[STG][3] = nullptr;
+        for (int c = 2; c < kBatchClasses; ++c) k.st[STG][c] = nullptr;
     }
 }
 
@@ -1338,11 +1347,12 @@ int radix_class(const std::vector<int>& rad) {
 }
 
 // per-problem launch parameters inside the batch tiles; rl / rt: radix
-// orders (empty: fixed rule).  Even m runs one real part per 128-thread theta
-// tile (DFT length m/2) when that tile holds it, otherwise the complex line
-// (DFT length m) in a 256-thread tile.
+// orders (empty: fixed rule).  Even m runs one real part per theta tile (DFT
+// length m/2) in one wave when the line fits it, else in 128 threads when it
+// fits those; otherwise the complex line (DFT length m) in a 256-thread tile.
+// *th_real: threads of the real-part tile, 0 for the complex line.
 bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, int* rwl, int* lam_nthr,
-                    int* th_fft, bool* th_real) {
+                    int* th_fft, int* th_real) {
     const int N = n / 2;
     if (!valid_radices(rl, N)) rl.clear();
     if (rl.empty() && !factorize(N, rl)) return false;
@@ -1357,17 +1367,19 @@ bool batch_schedule(int n, int m, std::vector<int>& rl, std::vector<int>& rt, in
     }
     *rwl = best;
     *lam_nthr = t;
-    *th_real = false;
+    *th_real = 0;
     if ((m & 1) == 0) {
         std::vector<int> r = rt;
         if (!valid_radices(r, m / 2)) r.clear();
         if (!r.empty() || factorize(m / 2, r)) {
             const int f = fft_threads(r, m / 2);
-            const int need = std::max(std::max(f, solve_threads(m, kSmaxR)), sp::real_theta_min_threads(m));
-            if (need <= kBatchRealThreads) {
+            const int base = std::max(f, sp::real_theta_min_threads(m));
+            const int nt = std::max(base, solve_threads(m, kSmaxR)) <= kBatchWaveThreads ? kBatchWaveThreads
+                         : std::max(base, solve_threads(m, kBatchSmaxR)) <= kBatchRealThreads ? kBatchRealThreads : 0;
+            if (nt) {
                 rt = r;
                 *th_fft = f;
-                *th_real = true;
+                *th_real = nt;
                 return true;
             }
         }
@@ -1412,19 +1424,19 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     }
     std::vector<int> rwl(count), lnt(count), tft(count);
     std::vector<std::vector<int>> rls(count), rts(count);
-    std::vector<char> treal(count);
+    std::vector<int> treal(count);
     for (int r = 0; r < count; ++r) {
         Sched sc = cached_schedule(n[r], m[r], precision);
         rls[r] = sc.lam;
         rts[r] = sc.theta;
-        bool re = false;
+        int re = 0;
         if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r], &re)) {
             rls[r].clear();
             rts[r].clear();
             if (!batch_schedule(n[r], m[r], rls[r], rts[r], &rwl[r], &lnt[r], &tft[r], &re))
                 return SP_ERR_UNSUPPORTED_SIZE;
         }
-        treal[r] = re ? 1 : 0;
+        treal[r] = re;
     }
 
     BatchPlan* bp = new (std::nothrow) BatchPlan();
@@ -1505,7 +1517,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     std::vector<int2> lam_items[kBatchClasses], th_items[kBatchClasses];
     size_t lam_lds_c[kBatchClasses] = {}, th_lds_c[kBatchClasses] = {};
     for (int r = 0; r < count; ++r) {
-        const int lc = radix_class(rls[r]), tc = radix_class(rts[r]) + (treal[r] ? 2 : 0);
+        const int lc = radix_class(rls[r]);
+        const int tc = radix_class(rts[r]) + (treal[r] == kBatchWaveThreads ? 4 : treal[r] ? 2 : 0);
         for (int jb = 0; jb < nblk[r]; ++jb) lam_items[lc].push_back(make_int2(r, jb));
         for (int k = 0; k <= n[r] / 2; ++k) {
             if (treal[r]) {
@@ -1516,7 +1529,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             }
         }
         lam_lds_c[lc] = std::max(lam_lds_c[lc], ((size_t)n[r] / 2 << rwl[r]) * sizeof(Cx<double>));
-        const size_t tl = treal[r] ? real_theta_lds_bytes(m[r], solve_threads(m[r], kSmaxR))
+        const int smaxr = treal[r] == kBatchWaveThreads ? kSmaxR : kBatchSmaxR;
+        const size_t tl = treal[r] ? real_theta_lds_bytes(m[r], solve_threads(m[r], smaxr))
                                    : theta_lds_bytes<double>(m[r], std::max(solve_threads(m[r], kSmaxD),
                                                                             solve_threads(m[r], kSmaxF)));
         th_lds_c[tc] = std::max(th_lds_c[tc], tl);
@@ -1558,7 +1572,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         const SizeTables& T = th[tkey[r]];
         sp::RhsDesc& d = descs[r];
         d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r]; d.lay_log2 = rwl[r];
-        d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r]; d.theta_real = treal[r];
+        d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r]; d.theta_real = treal[r] ? 1 : 0;
         d.k64 = std::max(16, m[r] / 64);
         d.c0 = 0.0;
         d.fl = L.desc; d.ft = T.desc;
@@ -1671,7 +1685,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             if (lds + 1024 > lds_limit) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
             Launch L;
             L.fn = K.st[stg][c];
-            L.nt = c >= 2 ? kBatchRealThreads : kBatchThreads;
+            L.nt = c >= 4 ? kBatchWaveThreads : c >= 2 ? kBatchRealThreads : kBatchThreads;
             (void)hipFuncSetAttribute((const void*)L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             int occ = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)L.fn, L.nt, lds) !=

@@ -41,7 +41,8 @@ def run(P, f, integral=0.0, **kw):
 
 
 @pytest.mark.parametrize("n,m", [(64, 64), (4, 4), (40, 21), (150, 75), (210, 143), (62, 31),
-                                 (128, 2048), (2048, 128), (1984, 1984), (1024, 1024)])
+                                 (128, 2048), (2048, 128), (1984, 1984), (1024, 1024), (10000, 40),
+                                 (40, 10000)])
 def test_mixed_matches_oracle(P, n, m):
     print("mixed", n, m, flush=True)
     L = max(1, min(n // 2 - 1, m - 3, 40))

@@ -42,8 +42,11 @@ def field(n, m, L, seed, with_solution=False):
     return S.sphere_field(seed, 0, n, m, L, with_solution=with_solution)
 
 
+# (10000, 40) and (40, 10000): the compiled-in length-5000 transform in the
+# lambda direction alone, and in the theta direction (real parts, m/2 = 5000)
+# alone, each with a short ragged other direction
 SIZES = [(64, 64), (4, 4), (8, 4), (40, 21), (150, 75), (96, 60), (210, 143), (68, 38), (46, 58),
-         (62, 31), (128, 2048), (2048, 128), (1984, 1984), (256, 200)]
+         (62, 31), (128, 2048), (2048, 128), (1984, 1984), (256, 200), (10000, 40), (40, 10000)]
 
 
 @pytest.mark.parametrize("n,m", SIZES)
