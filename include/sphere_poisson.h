@@ -129,12 +129,16 @@ int sphere_poisson_solve(sp_plan plan, const double* f, double* u, double integr
 int sphere_poisson_solve_adjoint(sp_plan plan, const double* g, double* fbar,
                                  void* hip_stream, sp_info* info);
 
-/* Solve `count` independent problems of possibly different sizes in one
- * persistent launch captured in a HIP graph.  n[r], m[r]: sizes of problem r
- * (host arrays); f[r], u[r]: device pointers (host arrays of pointers).
+/* Solve `count` independent problems of possibly different sizes with one
+ * launch of a HIP graph (one persistent kernel per solve stage and kernel
+ * build, each taking (problem, tile) items from a work list).  n[r], m[r]:
+ * sizes of problem r (host arrays); f[r], u[r]: device pointers (host arrays
+ * of pointers), each [m[r]][n[r]] float64; every problem uses integral = 0.
  * The batch plan (workspace, schedules per distinct size, graph) is built on
  * the first call for a given size list and reused while the list and the
- * pointers are unchanged.  `infos` may be NULL (else `count` entries).
+ * pointers are unchanged.  In SP_MIXED, u[r] is scratch until the graph ends,
+ * as in sphere_poisson_solve.  `infos` may be NULL (else `count` entries;
+ * filled after a synchronisation of `hip_stream`).
  * Errors: as sphere_poisson_plan and sphere_poisson_solve. */
 int sphere_poisson_solve_batch(int count, const int* n, const int* m,
                                const double* const* f, double* const* u,
