@@ -139,6 +139,9 @@ int sphere_poisson_solve_adjoint(sp_plan plan, const double* g, double* fbar,
  * pointers are unchanged.  In SP_MIXED, u[r] is scratch until the graph ends,
  * as in sphere_poisson_solve.  `infos` may be NULL (else `count` entries;
  * filled after a synchronisation of `hip_stream`).
+ * Every problem must fit the batch tiles (256 threads): n/2 up to about 4096
+ * and m up to about 3300 (the exact bounds depend on the radices);
+ * SP_ERR_UNSUPPORTED_SIZE otherwise.
  * Errors: as sphere_poisson_plan and sphere_poisson_solve. */
 int sphere_poisson_solve_batch(int count, const int* n, const int* m,
                                const double* const* f, double* const* u,
