@@ -287,43 +287,53 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
 
 // u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
 // weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].  u0 is
-// the copy the mix pass left at the start of each output row (every row is
-// read into LDS before any of the tile's rows is overwritten).
+// the copy the mix pass left at the start of each output row; every thread
+// reads the values it combines into registers before the first barrier, so
+// no row is overwritten before it has been read.  LDS per row: N float32
+// complex (the correction line only).
 // Optionally accumulates per-block sums of (s d)^2 and u^2.
 template <int EPT, int RMAX>
 __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw,
                                                    double (*red)[16]) {
-    Cx<float>* fl = reinterpret_cast<Cx<float>*>(smem_raw);   // row r: [u0 line | d line]
+    Cx<float>* fl = reinterpret_cast<Cx<float>*>(smem_raw);   // row r: the correction line
     const int N = a.N;
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
-    const size_t stride = 2 * (size_t)N;
-    Cx<float>* b0 = fl + (size_t)line * stride;
-    Cx<float>* b1 = b0 + N;
+    constexpr int H = LineHold<EPT, RMAX>::value;
+    Cx<float> u0[H];
     if (!a.accumulate && active) {
         const Cx<float>* keep = reinterpret_cast<const Cx<float>*>(a.u + (size_t)j * a.n);
-        for (int i = t; i < N; i += a.nthr) b0[i] = keep[i];
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            const int i = t + e * a.nthr;
+            if (i < N) u0[e] = keep[i];
+        }
     }
-    c2r_load_prepare<float, float>(fl + N, stride, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
+    c2r_load_prepare<float, float>(fl, (size_t)N, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
                                    a.in_w_end);
     __syncthreads();
-    fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N + N, a.fft, a.ptw32, t, a.nthr, active);
+    fft_lds<float, true, EPT, RMAX>(fl, line * N, a.fft, a.ptw32, t, a.nthr, active);
+    const Cx<float>* b1 = fl + (size_t)line * N;
     double sd2 = 0.0, su2 = 0.0;
     if (active) {
         const double sc = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
         double2* dst = reinterpret_cast<double2*>(a.u + (size_t)j * a.n);
-        for (int i = t; i < N; i += a.nthr) {
-            const Cx<float> d = b1[i];
-            const double dx = (double)d.x * sc, dy = (double)d.y * sc;
-            double2 base;
-            if (a.accumulate) base = dst[i];
-            else base = double2{(double)b0[i].x * sc, (double)b0[i].y * sc};
-            const double2 v = double2{base.x + dx, base.y + dy};
-            dst[i] = v;
-            sd2 += dx * dx + dy * dy;
-            su2 += v.x * v.x + v.y * v.y;
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            const int i = t + e * a.nthr;
+            if (i < N) {
+                const Cx<float> d = b1[i];
+                const double dx = (double)d.x * sc, dy = (double)d.y * sc;
+                double2 base;
+                if (a.accumulate) base = dst[i];
+                else base = double2{(double)u0[e].x * sc, (double)u0[e].y * sc};
+                const double2 v = double2{base.x + dx, base.y + dy};
+                dst[i] = v;
+                sd2 += dx * dx + dy * dy;
+                su2 += v.x * v.x + v.y * v.y;
+            }
         }
     }
     if (a.partial) {

@@ -1183,7 +1183,8 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
             ma.accumulate = it > 1 ? 1 : 0;
             {
                 ProfScope ps(p, SP_KERNEL_LAMBDA_UPD, s);
-                hipLaunchKernelGGL(p->km.update, lam_grid, lam_block, p->lam_lds, s, ma);
+                // float32 correction lines only: half the LDS of the other lambda passes
+                hipLaunchKernelGGL(p->km.update, lam_grid, lam_block, p->lam_lds / 2, s, ma);
             }
         }
         if (want) {
@@ -1681,7 +1682,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         for (int c = 0; c < kBatchClasses; ++c) {
             const int nit = (int)(is_theta ? th_items[c].size() : lam_items[c].size());
             if (nit == 0) continue;
-            const size_t lds = is_theta ? th_lds_c[c] : lam_lds_c[c];
+            // the update holds float32 correction lines only: half a float64 lambda tile
+            const size_t lds = is_theta ? th_lds_c[c] : stg == sp::kBLamUpd ? lam_lds_c[c] / 2 : lam_lds_c[c];
             if (lds + 1024 > lds_limit) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
             Launch L;
             L.fn = K.st[stg][c];
