@@ -24,3 +24,4 @@ come from the oracle itself (the paper's worked integral, the paper's
 eigenvalue statement, closed-form solutions, brute-force dense solves).
 """
 from .sphere_poisson import *  # noqa: F401,F403
+from .calculus import *  # noqa: F401,F403

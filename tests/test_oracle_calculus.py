@@ -1,0 +1,112 @@
+"""Pins of the tangential-derivative oracle (Section 4, eq. diff_x/y/z, dfdx,
+Msin) against closed forms that do not come from the oracle: the surface
+gradient of the restriction of a polynomial F(x, y, z) is
+grad F - (p . grad F) p, and the paper's worked example
+d^t cos(theta)/dx = -x z."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.calculus as OC
+import sh_inputs as S
+from conftest import rel2
+
+
+def _grid_xyz(m, n):
+    th = O.theta_grid(m)[:, None]
+    lam = O.lambda_grid(n)[None, :]
+    return np.cos(lam) * np.sin(th), np.sin(lam) * np.sin(th), np.cos(th) * np.ones_like(lam)
+
+
+def _rel3(a, b):
+    num = sum(np.linalg.norm(x - y) ** 2 for x, y in zip(a, b))
+    den = sum(np.linalg.norm(y) ** 2 for y in b)
+    return float(np.sqrt(num / den))
+
+
+# a random quartic: F = sum c_abc x^a y^b z^c over a + b + c <= 4
+_EXPS = [(a, b, c) for a in range(5) for b in range(5) for c in range(5) if a + b + c <= 4]
+_COEF = np.random.default_rng(7).standard_normal(len(_EXPS))
+
+
+def _quartic(x, y, z):
+    return sum(c * x ** a * y ** b * z ** e for c, (a, b, e) in zip(_COEF, _EXPS))
+
+
+def _quartic_grad(x, y, z):
+    gx = sum(c * a * x ** max(a - 1, 0) * y ** b * z ** e for c, (a, b, e) in zip(_COEF, _EXPS) if a)
+    gy = sum(c * b * x ** a * y ** max(b - 1, 0) * z ** e for c, (a, b, e) in zip(_COEF, _EXPS) if b)
+    gz = sum(c * e * x ** a * y ** b * z ** max(e - 1, 0) for c, (a, b, e) in zip(_COEF, _EXPS) if e)
+    return gx, gy, gz
+
+
+def test_paper_example_cos_theta():
+    """Section 4: applying d^t/dx to cos(theta) gives -x z on the sphere; the
+    other components of the surface gradient of z are -y z and 1 - z^2."""
+    m, n = 12, 16
+    x, y, z = _grid_xyz(m, n)
+    gx, gy, gz = O.tangential_gradient(z.copy())
+    assert np.max(np.abs(gx + x * z)) <= 1e-13
+    assert np.max(np.abs(gy + y * z)) <= 1e-13
+    assert np.max(np.abs(gz - (1 - z * z))) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(12, 16), (9, 10), (16, 12), (31, 40)])
+def test_quartic_closed_form(m, n):
+    x, y, z = _grid_xyz(m, n)
+    got = O.tangential_gradient(_quartic(x, y, z))
+    ref = O.polynomial_surface_gradient(_quartic_grad, m, n)
+    assert _rel3(got, ref) <= 1e-12
+
+
+def test_gradient_is_tangent():
+    m, n = 40, 48
+    f = S.sphere_field(31, 0, n, m, 12)
+    gx, gy, gz = O.tangential_gradient(f)
+    x, y, z = _grid_xyz(m, n)
+    scale = np.sqrt(np.mean(gx ** 2 + gy ** 2 + gz ** 2))
+    assert np.max(np.abs(x * gx + y * gy + z * gz)) <= 1e-12 * scale
+
+
+def test_dirichlet_energy_identity():
+    """Green's identity on the closed sphere: for u with Delta u = f, the
+    integral of |grad_s u|^2 equals minus the integral of u f.  u and f are
+    the generator's closed-form pair (f a band-limited harmonic field,
+    u = -sum c Y / (l (l + 1))); the integrals use the paper's quadrature
+    (sum2), exact for these band limits."""
+    m, n, L = 48, 64, 10
+    f, u = S.sphere_field(33, 0, n, m, L, with_solution=True)
+    gx, gy, gz = O.tangential_gradient(u)
+    lhs = O.surface_integral(gx * gx + gy * gy + gz * gz)
+    rhs = -O.surface_integral(u * f)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+def test_planted_transposed_msin_is_caught(monkeypatch):
+    real = OC.msin_matrix
+    monkeypatch.setattr(OC, "msin_matrix", lambda M: real(M).T)
+    m, n = 12, 16
+    x, y, z = _grid_xyz(m, n)
+    got = OC.tangential_gradient(_quartic(x, y, z))
+    ref = OC.polynomial_surface_gradient(_quartic_grad, m, n)
+    assert _rel3(got, ref) > 1e-3
+
+
+def test_planted_reversed_sine_shift_is_caught(monkeypatch):
+    real = OC._times_sin
+    monkeypatch.setattr(OC, "_times_sin", lambda C, axis: -real(C, axis))
+    m, n = 12, 16
+    x, y, z = _grid_xyz(m, n)
+    got = OC.tangential_gradient(_quartic(x, y, z))
+    ref = OC.polynomial_surface_gradient(_quartic_grad, m, n)
+    assert _rel3(got, ref) > 1e-3
+
+
+def test_planted_printed_z_sign_is_caught():
+    """The z component with the sign as printed (+sin(theta) d/dtheta) fails
+    the closed form: the minus sign is the chain rule's."""
+    m, n = 12, 16
+    x, y, z = _grid_xyz(m, n)
+    gx, gy, gz = O.tangential_gradient(_quartic(x, y, z))
+    ref = O.polynomial_surface_gradient(_quartic_grad, m, n)
+    assert _rel3((gx, gy, -gz), ref) > 1e-3
