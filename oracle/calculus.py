@@ -87,7 +87,11 @@ def tangential_gradient(f: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarr
     samples f[j, i] at theta_j = (j + 1/2) pi / m, lambda_i = -pi + 2 pi i / n."""
     m, n = f.shape
     M = 2 * m
-    X = coeffs2(dfs_double(f))                      # q = -m..m-1 rows, k = -n/2..n/2-1 columns
+    # q = -m..m-1 rows, k = -n/2..n/2-1 columns.  The FFT evaluation (the
+    # paper's route, Section 4 "Computation of Fourier coefficients"): the
+    # explicit sums round the phase q theta to about q theta eps, an error the
+    # derivative then multiplies by q (1e-12 at m = 75).
+    X = coeffs2(dfs_double(f), method="fft")
     qs = np.arange(-m, m)
     ks = np.arange(-n // 2, n // 2)
     dq = 1j * qs.astype(np.float64)

@@ -110,3 +110,13 @@ def test_planted_printed_z_sign_is_caught():
     gx, gy, gz = O.tangential_gradient(_quartic(x, y, z))
     ref = O.polynomial_surface_gradient(_quartic_grad, m, n)
     assert _rel3((gx, gy, -gz), ref) > 1e-3
+
+
+def test_refined_grid_agrees_on_common_rows():
+    """The same band-limited field sampled with 3m rows contains the m-row
+    nodes (theta at rows 3j + 1): the gradient there must agree (a property of
+    the exact result, independent of the grid)."""
+    n, m, L = 150, 75, 40
+    a = O.tangential_gradient(S.sphere_field(41, 0, n, m, L))
+    b = O.tangential_gradient(S.sphere_field(41, 0, n, 3 * m, L))
+    assert _rel3(a, tuple(c[1::3] for c in b)) <= 1e-13
