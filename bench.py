@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -50,6 +51,8 @@ def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
         "theta_resid": 2 * spec64 + spec32,
         # update: reads the kept float32 rows and the correction spectrum, writes u
         "lambda_upd": grid // 2 + spec32 + grid,
+        # tangential gradient: both float64 spectra read, three components written
+        "lambda_grad": 2 * spec64 + 3 * grid,
     }
     return table[kind]
 
@@ -103,6 +106,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the tangential-gradient measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 800 MB device-to-device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -225,6 +229,8 @@ def main():
             out["rel_err_vs_oracle"] = float(np.linalg.norm(u - u_or) / np.linalg.norm(u_or))
     plan.close()
     del fg, ug
+    if not args.no_gradient:
+        out["gradient"] = bench_gradient(args, P, torch, n, m)
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
@@ -249,6 +255,54 @@ def copy_calibration(args, torch):
     nbytes = 2 * x.numel() * 8
     print(json.dumps({"copy_bytes_per_launch": nbytes, "read_bytes": nbytes // 2, "write_bytes": nbytes // 2,
                       "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def bench_gradient(args, P, torch, n, m):
+    """Tangential gradient (d^t/dx, d^t/dy, d^t/dz of Section 4) of
+    F = x y z + z^2 - 3 x^2 y on the workload grid, float64: time per call
+    (inputs resident), library HIP-event kernel times, error against the
+    closed form grad F - (p . grad F) p on every 97th row."""
+    dev = torch.device("cuda", 0)
+    # grid nodes theta_j = (j + 1/2) pi / m, lambda_i = -pi + 2 pi i / n
+    th = ((torch.arange(m, dtype=torch.float64, device=dev) + 0.5) * (math.pi / m))[:, None]
+    lam = (-math.pi + torch.arange(n, dtype=torch.float64, device=dev) * (2.0 * math.pi / n))[None, :]
+    x, y, z = torch.cos(lam) * torch.sin(th), torch.sin(lam) * torch.sin(th), torch.cos(th).expand(m, n)
+    f = (x * y * z + z * z - 3 * x * x * y).contiguous()
+    plan = P.SpherePoisson(n, m, "fp64")
+    outs = [torch.empty_like(f) for _ in range(3)]
+    for _ in range(max(1, args.warmup)):
+        plan.tangential_gradient(f, outs=outs)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    plan.profile_enable(3 * steps)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.tangential_gradient(f, outs=outs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    prof = plan.profile_read()
+    plan.profile_enable(0)
+    rows = torch.arange(0, m, 97, device=dev)
+    xs, ys, zs = x[rows], y[rows], z[rows]
+    Fx, Fy, Fz = ys * zs - 6 * xs * ys, xs * zs - 3 * xs * xs, xs * ys + 2 * zs
+    rad = xs * Fx + ys * Fy + zs * Fz
+    ref = (Fx - rad * xs, Fy - rad * ys, Fz - rad * zs)
+    err = torch.sqrt(sum(((o[rows] - r) ** 2).sum() for o, r in zip(outs, ref)) / sum((r ** 2).sum() for r in ref))
+    kinds = {"lambda_fwd": "lambda_fwd", "theta": "theta_deriv", "lambda_grad": "lambda_grad"}
+    kern = {}
+    for k, (tot, cnt) in prof.items():
+        alg = kernel_bytes(k, n, m, "fp64")
+        avg = tot / cnt
+        kern[kinds.get(k, k)] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": alg,
+                                 "alg_GBps": round(alg / (avg * 1e-3) / 1e9, 1)}
+    plan.close()
+    log("bench: gradient %.3f ms/call, %.3e DOF/s, rel err %.2e" % (ms, n * m / (ms * 1e-3), float(err)))
+    return {"workload": "tangential_gradient_n%d_m%d_fp64" % (n, m), "ms_per_call": ms,
+            "dof_per_s": n * m / (ms * 1e-3), "alg_bytes_per_dof": 72, "kernels": kern,
+            "rel_err_vs_closed_form": float(err)}
 
 
 def bench_batch(args, P, S, torch, np):

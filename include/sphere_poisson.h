@@ -153,6 +153,25 @@ int sphere_poisson_destroy(sp_plan plan);
 /* Human-readable text for a status code (static storage). */
 const char* sphere_poisson_strerror(int code);
 
+/* Tangential derivatives of a grid function (Section 4, "Differentiation",
+ * eq. diff_x, diff_y, diff_z): the Cartesian components of the surface
+ * gradient,
+ *   gx = -(sin lambda / sin theta) df/dlambda + cos lambda cos theta df/dtheta,
+ *   gy =  (cos lambda / sin theta) df/dlambda + sin lambda cos theta df/dtheta,
+ *   gz = -sin theta df/dtheta
+ * (the z component with the chain rule's sign; the paper prints it with a
+ * plus sign).  f: input, gx, gy, gz: outputs, all device [m][n] float64 on the
+ * plan's grid, pairwise non-overlapping (SP_ERR_ALIAS).  The derivatives are
+ * spectral (exact for band-limited f, in float64 whatever the plan's
+ * precision); sin(theta) never vanishes on the half-shifted theta grid, so
+ * the division is by the node values.  Asynchronous on `hip_stream`; uses the
+ * plan's workspace, so calls on one plan must not overlap.
+ * Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG, SP_ERR_ALIAS, SP_ERR_HIP,
+ * SP_ERR_UNSUPPORTED_SIZE when two float64 rows of n/2 complex values do not
+ * fit the LDS (n above about 10240). */
+int sphere_poisson_tangential_gradient(sp_plan plan, const double* f, double* gx, double* gy, double* gz,
+                                       void* hip_stream);
+
 /* Bytes of device workspace a plan for `desc` would allocate (0 on invalid desc). */
 size_t sphere_poisson_workspace_bytes(const sp_desc* desc);
 
@@ -172,7 +191,8 @@ typedef enum {
     SP_KERNEL_THETA_RESID = 4,  /* MIXED: float64 residual in coefficient space + float32 correction solve */
     SP_KERNEL_LAMBDA_UPD = 5,   /* MIXED: float32 inverse lambda DFT of the correction + float64 update of u */
     SP_KERNEL_REDUCE = 6,       /* norms for the convergence report */
-    SP_KERNEL_KINDS = 7
+    SP_KERNEL_LAMBDA_GRAD = 7,  /* tangential gradient: both inverse lambda DFTs of a row, combined */
+    SP_KERNEL_KINDS = 8
 } sp_kernel_kind;
 
 /* Diagnostic profiling: with `capacity` > 0 every later kernel launch of this

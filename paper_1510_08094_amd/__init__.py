@@ -83,11 +83,12 @@ def library():
     lib.sphere_poisson_workspace_bytes.argtypes = [ctypes.POINTER(SpDesc)]
     lib.sphere_poisson_workspace_bytes.restype = ctypes.c_size_t
     lib.sphere_poisson_transform_roundtrip.argtypes = [vp, vp, vp, vp]
+    lib.sphere_poisson_tangential_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sphere_poisson_profile_enable.argtypes = [vp, ci]
     lib.sphere_poisson_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
     for name in ("sphere_poisson_profile_enable", "sphere_poisson_profile_read", "sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
-                 "sphere_poisson_transform_roundtrip"):
+                 "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -163,7 +164,21 @@ class SpherePoisson:
                 ctypes.c_void_p(_stream_handle(self.device))))
         return out
 
-    KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce")
+    def tangential_gradient(self, f: torch.Tensor, outs=None):
+        """(d^t f/dx, d^t f/dy, d^t f/dz) on the plan's grid (Section 4, eq.
+        diff_x, diff_y, diff_z; float64 whatever the plan's precision)."""
+        _check_grid(f, self.m, self.n, "f")
+        gs = [torch.empty_like(f) for _ in range(3)] if outs is None else list(outs)
+        for g in gs:
+            _check_grid(g, self.m, self.n, "out")
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_tangential_gradient(
+                self._plan, ctypes.c_void_p(f.data_ptr()), *(ctypes.c_void_p(g.data_ptr()) for g in gs),
+                ctypes.c_void_p(_stream_handle(self.device))))
+        return tuple(gs)
+
+    KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce",
+                    "lambda_grad")
 
     def profile_enable(self, capacity: int):
         """Bracket the next `capacity` kernel launches with HIP events."""

@@ -1,0 +1,83 @@
+// Tangential derivatives on the sphere (Section 4, "Differentiation"): the
+// Cartesian components of the surface gradient,
+//   d^t/dx = -(sin lambda / sin theta) d/dlambda + cos lambda cos theta d/dtheta,
+//   d^t/dy =  (cos lambda / sin theta) d/dlambda + sin lambda cos theta d/dtheta,
+//   d^t/dz = -sin theta d/dtheta
+// (the z component's sign is the chain rule's, z = cos theta).  As in the
+// paper, the division by sin(theta) is done on coefficients (eq. Msin): the
+// theta pass in divide mode turns each wavenumber's series into that of the
+// series divided by sin(theta), and the theta pass in derivative mode writes
+// the theta derivative.  This pass runs both inverse lambda transforms of a
+// row (the first with the factor i k of d/dlambda) and combines them with the
+// node values of sin/cos lambda and cos/sin theta.  Dividing on the grid
+// instead (the nodes never include a pole) amplifies rounding near the poles
+// by up to 1/sin(theta_0) ~ 2m/pi.
+#pragma once
+#include "sp_kernels.hpp"
+
+namespace sp {
+
+struct GradArgs {
+    const Cx<double>* spec_q;   // half spectrum of f / sin(theta) (theta pass, divide mode)
+    const Cx<double>* spec_t;   // half spectrum of d f / d theta (theta pass, derivative mode)
+    double* gx;                 // outputs [m][n]
+    double* gy;
+    double* gz;
+    const Cx<double>* tw;       // e^{-2 pi i t/n}
+    const Cx<double>* ptw;      // per-pass twiddles of the length-N DFT
+    const double* rowtab;       // per row j: cos(theta_j), sin(theta_j)  ([2][m])
+    const double* coltab;       // per column i: sin(lambda_i), cos(lambda_i)             ([2][n])
+    int n, m, N, rw_log2;
+    int lay_log2;               // run length (log2) of both spectra read
+    FftDesc fft;
+    int nthr;                   // threads per row
+};
+
+// LDS per row: two lines of N float64 complex ((d/dlambda) / sin(theta), then d/dtheta).
+template <int EPT, int RMAX>
+__device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsigned char* smem_raw) {
+    Cx<double>* lines = reinterpret_cast<Cx<double>*>(smem_raw);
+    const int N = a.N;
+    const int line = threadIdx.x / a.nthr;
+    const int t = threadIdx.x - line * a.nthr;
+    const int j = (jb << a.rw_log2) + line;
+    const bool active = line < (1 << a.rw_log2) && j < a.m;
+    const size_t stride = 2 * (size_t)N;
+    c2r_load_prepare<double, double, true>(lines, stride, a.spec_q, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
+                                           1.0);
+    c2r_load_prepare<double, double>(lines + N, stride, a.spec_t, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
+                                     1.0);
+    __syncthreads();
+    fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N, a.fft, a.ptw, t, a.nthr, active);
+    fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N + N, a.fft, a.ptw, t, a.nthr, active);
+    if (active) {
+        const Cx<double>* fl = lines + (size_t)line * stride;   // samples 2i, 2i+1 of (d f/d lambda) / sin(theta)
+        const Cx<double>* ft = fl + N;                            // and of d f/d theta
+        const double cst = a.rowtab[j], snt = a.rowtab[a.m + j];
+        const double2* sl = reinterpret_cast<const double2*>(a.coltab);
+        const double2* cl = reinterpret_cast<const double2*>(a.coltab + a.n);
+        double2* ox = reinterpret_cast<double2*>(a.gx + (size_t)j * a.n);
+        double2* oy = reinterpret_cast<double2*>(a.gy + (size_t)j * a.n);
+        double2* oz = reinterpret_cast<double2*>(a.gz + (size_t)j * a.n);
+        for (int i = t; i < N; i += a.nthr) {
+            const Cx<double> dl = fl[i], dt = ft[i];
+            const double2 s = sl[i], c = cl[i];
+            // samples 2i (.x) and 2i+1 (.y)
+            const double ax = dl.x, ay = dl.y;
+            const double bx = dt.x * cst, by = dt.y * cst;
+            ox[i] = double2{-s.x * ax + c.x * bx, -s.y * ay + c.y * by};
+            oy[i] = double2{c.x * ax + s.x * bx, c.y * ay + s.y * by};
+            oz[i] = double2{-snt * dt.x, -snt * dt.y};
+        }
+    }
+}
+
+template <int EPT, int RMAX>
+__global__ void __launch_bounds__(1024) k_lambda_grad(GradArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
+    if (jb << a.rw_log2 >= a.m) return;
+    lambda_grad_body<EPT, RMAX>(a, jb, smem_raw);
+}
+
+}  // namespace sp

@@ -90,7 +90,10 @@ __device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t strid
 
 // Read the half spectrum of every row (type TS, times w_mid / w_end) and build
 // the length-N complex sequence whose inverse DFT interleaves the real output.
-template <typename T, typename TS>
+// DLAM: the spectrum of d/dlambda instead, coefficient k times i k; the k = 0
+// and k = n/2 terms vanish (the derivative of the real Nyquist mode is zero on
+// the grid).
+template <typename T, typename TS, bool DLAM = false>
 __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, const Cx<TS>* spec,
                                                  const Cx<T>* tw, int N, int rwl, int lay, int m, int jb,
                                                  T w_mid, T w_end) {
@@ -103,15 +106,23 @@ __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, co
         if (j >= m) continue;
         Cx<T>* b = lines + (size_t)jj * stride;
         if (k == 0) {
-            const T x0 = (T)spec[spec_at(j, 0, N, lay)].x * w_end;
-            const T xN = (T)spec[spec_at(j, N, N, lay)].x * w_end;
-            b[0] = Cx<T>{x0 + xN, x0 - xN};
+            if constexpr (DLAM) {
+                b[0] = Cx<T>{(T)0, (T)0};
+            } else {
+                const T x0 = (T)spec[spec_at(j, 0, N, lay)].x * w_end;
+                const T xN = (T)spec[spec_at(j, N, N, lay)].x * w_end;
+                b[0] = Cx<T>{x0 + xN, x0 - xN};
+            }
             continue;
         }
         const Cx<TS> sk = spec[spec_at(j, k, N, lay)];
         const Cx<TS> sn = spec[spec_at(j, N - k, N, lay)];
-        const Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
-        const Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
+        Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
+        Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
+        if constexpr (DLAM) {
+            xk = mul_i(xk) * (T)k;
+            xn = mul_i(xn) * (T)(N - k);
+        }
         const Cx<T> P = xk + cconj(xn);
         const Cx<T> Q = xk - cconj(xn);
         const Cx<T> iWQ = mul_i(cmulc(Q, tw[k]));   // i conj(W) Q
@@ -395,7 +406,46 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double* partial, 
 // neighbours are dropped.  For k = 0 (cosine) the q = 0 row is replaced by the
 // integral constraint a_0 = c0 - sum_{q>=2 even} a_q / (1 - q^2).
 
-enum ThetaMode { kSolve = 0, kSolveTransposed = 1, kTransformOnly = 2 };
+enum ThetaMode { kSolve = 0, kSolveTransposed = 1, kTransformOnly = 2, kDerivative = 3, kDivideSin = 4 };
+
+constexpr int kThetaHold = 16;   // positions per thread in the residual / conversion loops, complex-line derivative
+
+// d/dtheta of a column held as true coefficients in position order (a cosine
+// series, coefficient q at position q, for even k; a sine series, coefficient
+// q at position m - q, for odd k).  The derivative of a cosine series is the
+// sine series with coefficients -q a_q, and that of a sine series the cosine
+// series with coefficients q b_q; in both cases the new value at position p
+// comes from position m - p:
+//   even k: out[p] = -(m - p) in[m - p],   odd k: out[p] = p in[m - p],
+// and out[0] = 0: for even k it would be the sine coefficient q = m, which
+// needs a cosine coefficient q = m that the series does not have; for odd k it
+// is the constant term of the derivative.  (The derivative of the sine term
+// q = m, at position 0, is a multiple of cos(m theta), zero at every grid
+// node.)  The column is then synthesised with the other parity.
+// HOLD >= m / nthr.
+template <typename V> struct ScalarOf { using type = V; };
+template <typename T> struct ScalarOf<Cx<T>> { using type = T; };
+
+template <typename V, int HOLD>
+__device__ __forceinline__ void theta_derivative_line(V* y, int m, bool sine, int tid, int nthr) {
+    using S = typename ScalarOf<V>::type;
+    V h[HOLD];
+#pragma unroll
+    for (int e = 0; e < HOLD; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) {
+            const S w = p == 0 ? (S)0 : (sine ? (S)p : -(S)(m - p));
+            h[e] = p == 0 ? V{} : y[m - p] * w;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < HOLD; ++e) {
+        const int p = tid + e * nthr;
+        if (p < m) y[p] = h[e];
+    }
+    __syncthreads();
+}
 
 template <typename T>
 struct ThetaArgs {
@@ -873,6 +923,85 @@ __device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __r
     if (tid == 0) buf[0] = transposed ? V{} : vcast<V>(vfrom_real<VD>(c0) - dot);
 }
 
+// Division of a column by sin(theta) in coefficient space (the paper's
+// M_sin^{-1}, Section 4 eq. Msin, on the cosine / sine series of one
+// wavenumber instead of the doubled Fourier series).  With true coefficients
+// g_p in position order:
+//   even k, g a cosine series: h = g / sin(theta) is the sine series with
+//     c_{p+1} = 2 sum_{p' <= p, p' = p mod 2} g_p'   (from g_p = (c_{p+1} - c_{p-1}) / 2, g_0 = c_1 / 2),
+//     written at position m - (p + 1);
+//   odd k, g a sine series (g_p at position m - p, p = 1..m): h is the cosine series with
+//     d_{p-1} = 2 sum_{p' >= p, p' = p mod 2} g_p'   (from g_p = (d_{p-1} - d_{p+1}) / 2, g_1 = d_0 - d_2 / 2),
+//     halved for d_0, written at position p - 1.
+// These are cumulative sums along each parity class: every thread takes a
+// chunk of up to HOLD consecutive coefficients of one class, and the chunk
+// sums are scanned across the class (scan_affine, forward for even k,
+// backward for odd k).  The result is exact when g vanishes at both poles
+// (every wavenumber k >= 1 of a function on the sphere); the k = 0 column is
+// not divisible and its output is not used.  The column is then synthesised
+// with the other parity.  Uses the LDS from scratch (the line is read into
+// registers first).  2 ceil(ceil(m/2) / HOLD) <= blockDim.x.
+template <typename V, int HOLD>
+__device__ __forceinline__ void theta_divide_sin_line(V* y, unsigned char* scratch, int m, bool sine, int tid) {
+    using VD = typename VTraits<V>::D;
+    // coefficient range of the input: 0..m-1 (cosine) or 1..m (sine); classes by parity of p
+    const int plo = sine ? 1 : 0, phi = sine ? m : m - 1;
+    const int nE = (phi - (plo + (plo & 1)) ) / 2 + 1;                        // even p in [plo, phi]
+    const int firstO = plo | 1;
+    const int nO = phi >= firstO ? (phi - firstO) / 2 + 1 : 0;                // odd p
+    const int pE = (nE + HOLD - 1) / HOLD, pO = (nO + HOLD - 1) / HOLD;
+    const int ptot = pE + pO;
+    const bool inE = tid < pE, inO = !inE && tid < ptot;
+    const int c = inE ? tid : tid - pE;
+    const int ncls = inE ? nE : nO;
+    const int first = inE ? (plo + (plo & 1)) : firstO;   // first p of the class
+    const int lo = c * HOLD;
+    const int cnt = (inE || inO) ? min(HOLD, ncls - lo) : 0;
+    auto pos_in = [&](int p) { return sine ? m - p : p; };
+    V r[HOLD];
+    VD sum{};
+#pragma unroll
+    for (int ii = 0; ii < HOLD; ++ii) {
+        if (ii < cnt) {
+            r[ii] = y[pos_in(first + 2 * (lo + ii))];
+            sum = sum + vcast<VD>(r[ii]);
+        }
+    }
+    __syncthreads();   // the line is in registers; the LDS becomes scan scratch
+    double B = 1.0;
+    const int cls_lo = inE ? 0 : pE, cls_hi = inE ? pE : ptot;
+    scan_affine<VD, HOLD>(sum, B, scratch, tid, cls_lo, cls_hi, ptot, sine, cnt > 0);
+    VD* sa = reinterpret_cast<VD*>(scratch);
+    VD run{};
+    if (cnt > 0) {
+        const int o = sine ? tid + 1 : tid - 1;   // the neighbouring chunk already summed
+        if (sine ? (o < cls_hi) : (o >= cls_lo)) run = sa[o];
+    }
+    __syncthreads();   // scratch read; the line is written below
+    if (cnt > 0) {
+        if (!sine) {
+#pragma unroll
+            for (int ii = 0; ii < HOLD; ++ii) {
+                if (ii < cnt) {
+                    const int p = first + 2 * (lo + ii);
+                    run = run + vcast<VD>(r[ii]);
+                    y[m - (p + 1)] = vcast<V>(run * 2.0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int ii = HOLD - 1; ii >= 0; --ii) {
+                if (ii < cnt) {
+                    const int p = first + 2 * (lo + ii);
+                    run = run + vcast<VD>(r[ii]);
+                    y[p - 1] = vcast<V>(run * (p == 1 ? 1.0 : 2.0));
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int EPT, int RMAX, int SMAX>
 __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigned char* smem_raw,
                                            Cx<double>* red) {
@@ -897,7 +1026,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
     }
     __syncthreads();
     fft_lds<T, false, EPT, RMAX>(buf, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
-    const bool scale = a.mode == kSolve;
+    const bool scale = a.mode == kSolve || a.mode == kDerivative || a.mode == kDivideSin;
     for (int q = tid; q <= m / 2; q += nthr) {
         const int qq = q == 0 ? 0 : m - q;
         const Cx<T> A = buf[q], B = buf[qq];
@@ -913,12 +1042,17 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
         buf[q] = yq;
     }
     __syncthreads();
-    if (a.mode != kTransformOnly) {
+    if (a.mode == kDerivative) {
+        theta_derivative_line<Cx<T>, kThetaHold>(buf, m, sine, tid, nthr);
+    } else if (a.mode == kDivideSin) {
+        theta_divide_sin_line<Cx<T>, kThetaHold>(buf, smem_raw, m, sine, tid);
+    } else if (a.mode != kTransformOnly) {
         unsigned char* scratch = smem_raw;
         if (k == 0) solve_k0<T, SMAX>(buf, scratch, m, a.mode == kSolveTransposed, a.c0, a.k0tab, red, tid);
         else solve_partitioned<T, SMAX>(buf, scratch, m, k, sine, a.mode == kSolveTransposed, tid);
     }
     __syncthreads();
+    const bool sine_out = (a.mode == kDerivative || a.mode == kDivideSin) ? !sine : sine;
     for (int q = tid; q <= m / 2; q += nthr) {
         const int qq = q == 0 ? 0 : m - q;
         Cx<T> yq = buf[q], yqq = buf[qq];
@@ -943,7 +1077,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs<T>& a, int k, unsigne
         const size_t idx = spec_at(j, k, N, lay_out);
         const int pos = (j & 1) ? m - ((j + 1) >> 1) : (j >> 1);
         Cx<T> x = buf[pos] * invm;
-        if (sine && (j & 1)) x = Cx<T>{-x.x, -x.y};
+        if (sine_out && (j & 1)) x = Cx<T>{-x.x, -x.y};
         a.spec_out[idx] = x;
     }
 }
@@ -976,7 +1110,6 @@ __global__ void __launch_bounds__(1024) k_theta(ThetaArgs<T> a) {
 //   r = F - (L - k^2) X in float64 (k = 0: constraint row r_0 = c0 - (X_0 +
 //   sum_{q>=2 even} X_q/(1 - q^2))), solve for the correction in float32
 //   (k = 0 float64), float32 synthesis -> float32 spectrum sd.
-constexpr int kThetaHold = 16;   // positions per thread in the residual / conversion loops
 
 struct ThetaMixArgs {
     const Cx<double>* sa;      // float64 spectrum of sin^2 b (first solve)

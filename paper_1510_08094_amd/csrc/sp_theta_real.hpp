@@ -188,10 +188,14 @@ __device__ __forceinline__ void theta_real_body(const ThetaArgs<T>& a, int k, in
     }
     __syncthreads();
     fft_lds<T, false, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
-    const bool scale = a.mode == kSolve;
+    const bool scale = a.mode == kSolve || a.mode == kDerivative || a.mode == kDivideSin;
     const T invm = (T)1 / (T)m;
     rdct_split_forward<T>(z, a.eq, a.ws, m, scale ? invm : (T)1, scale ? (T)2 * invm : (T)1, tid, nthr);
-    if (a.mode != kTransformOnly) {
+    if (a.mode == kDerivative) {
+        theta_derivative_line<T, kRealLoadHold>(y, m, sine, tid, nthr);
+    } else if (a.mode == kDivideSin) {
+        theta_divide_sin_line<T, kRealLoadHold>(y, smem_raw, m, sine, tid);
+    } else if (a.mode != kTransformOnly) {
         const bool tr = a.mode == kSolveTransposed;
         if (k == 0) solve_k0<T, SMAX>(y, smem_raw, m, tr, part == 0 ? a.c0 : 0.0, a.k0tab, red, tid);
         else solve_partitioned<T, SMAX>(y, smem_raw, m, k, sine, tr, tid);
@@ -199,7 +203,8 @@ __device__ __forceinline__ void theta_real_body(const ThetaArgs<T>& a, int k, in
     }
     rdct_split_inverse<T>(y, a.eq, a.ws, m, scale ? (T)m : (T)1, scale ? (T)m * (T)0.5 : (T)1, tid, nthr);
     fft_lds<T, true, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
-    store_part<T, T>(y, a.spec_out, part, k, m, N, a.lay_out_log2, sine, invm, tid, nthr);
+    const bool flip = a.mode == kDerivative || a.mode == kDivideSin;
+    store_part<T, T>(y, a.spec_out, part, k, m, N, a.lay_out_log2, flip ? !sine : sine, invm, tid, nthr);
 }
 
 template <typename T, int EPT, int RMAX, int SMAX>

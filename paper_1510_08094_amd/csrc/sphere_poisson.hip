@@ -22,6 +22,7 @@
 #include "../../include/sphere_poisson.h"
 #include "sp_batch.hpp"
 #include "sp_theta_real.hpp"
+#include "sp_calculus.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
@@ -173,6 +174,11 @@ KernelSet<T> kernel_set() {
     return k;
 }
 
+void (*grad_kernel(int rs))(sp::GradArgs) {
+    if (rs == sp::kRadixFixed5000) return &sp::k_lambda_grad<kEPT, sp::kRadixFixed5000>;
+    return rs <= 16 ? &sp::k_lambda_grad<kEPT, 16> : &sp::k_lambda_grad<kEPT, 32>;
+}
+
 template <typename T>
 KernelSet<T> pick_kernels(int rs) {
     if (rs == sp::kRadixFixed5000) return kernel_set<T, sp::kRadixFixed5000>();
@@ -248,6 +254,11 @@ struct sp_plan_s {
     KernelSet<double> kd{};
     KernelSet<float> kf{};
     MixedSet km{};
+    // tangential gradient: lambda pass with two lines per row (null: the rows do not fit the LDS)
+    void (*grad)(sp::GradArgs) = nullptr;
+    int grad_rw_log2 = 0, grad_grid = 0, grad_block = 0;
+    size_t grad_lds = 0;
+    double* gradtab = nullptr;   // [2][m] cos(theta), sin(theta); then [2][n] sin(lambda), cos(lambda)
     // device memory
     void* block = nullptr;    // one allocation holding everything below
     size_t block_bytes = 0;
@@ -308,6 +319,7 @@ struct Layout {
     size_t off_ws64, off_ws32;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
     size_t off_specB, off_spec0, off_specd, off_partial, off_fco;
+    size_t off_grad;
     size_t spec_elems;
 };
 
@@ -334,6 +346,7 @@ Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
     L.off_k0 = take((size_t)2 * (m + 2) * sizeof(double));
     L.off_fint = take((size_t)m * sizeof(double));
     L.off_scal = take(16 * sizeof(double));
+    L.off_grad = take((size_t)(2 * m + 2 * n) * sizeof(double));
     // second float64 spectrum: the theta output of the float64 path (lambda
     // read layout), and in mixed plans the spectrum of the current iterate
     L.off_specB = take(L.spec_elems * sizeof(Cx<double>));
@@ -575,6 +588,22 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
             if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
+    // gradient pass: two float64 lines per row, as many rows per workgroup as fit (at most the plan's);
+    // the theta division by sin(theta) needs one thread per chunk of each parity class
+    const int div_hold = p->theta_real ? sp::kRealLoadHold : sp::kThetaHold;
+    const int div_threads = ceil_div((m + 1) / 2, div_hold) + ceil_div(m / 2, div_hold);
+    for (int g = p->rw_log2; g >= 0 && div_threads <= p->theta_threads; --g) {
+        const size_t lds = ((size_t)2 * N << g) * sizeof(Cx<double>);
+        if (lds + static_lds <= lds_limit) {
+            p->grad = grad_kernel(rs_lam);
+            p->grad_rw_log2 = g;
+            p->grad_lds = lds;
+            p->grad_block = round_up((1 << g) * p->lam_threads, 64);
+            p->grad_grid = round_up((m + (1 << g) - 1) >> g, 8 << (p->lay_log2 - g));
+            (void)hipFuncSetAttribute((const void*)p->grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            break;
+        }
+    }
     (void)hipGetLastError();
 
     // ---- device memory
@@ -604,6 +633,7 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     p->k0tab = (double*)(b + L.off_k0);
     p->fint_w = (double*)(b + L.off_fint);
     p->scal = (double*)(b + L.off_scal);
+    p->gradtab = (double*)(b + L.off_grad);
     p->specB = (Cx<double>*)(b + L.off_specB);
     if (mixed) {
         p->spec0 = (Cx<float>*)(b + L.off_spec0);
@@ -643,6 +673,21 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     if (ee == hipSuccess) ee = up(p->sin2, sin2.data(), m * sizeof(double));
     if (ee == hipSuccess) ee = up(p->k0tab, k0.data(), k0.size() * sizeof(double));
     if (ee == hipSuccess) ee = up(p->fint_w, fint.data(), m * sizeof(double));
+    // gradient factors: cos(theta_j), sin(theta_j); sin(lambda_i), cos(lambda_i)
+    // with lambda_i = -pi + 2 pi i/n, so (cos, sin)(lambda_i) = -(cos, sin)(2 pi i/n)
+    std::vector<double> gtab((size_t)2 * m + 2 * n);
+    for (int j = 0; j < m; ++j) {
+        const long double th = ((long double)j + 0.5L) * 3.141592653589793238462643383279502884L / (long double)m;
+        gtab[j] = (double)std::cos(th);
+        gtab[m + j] = (double)std::sin(th);
+    }
+    for (int i = 0; i < n; ++i) {
+        double c = 0.0, sn = 0.0;
+        cis_neg(i, n, &c, &sn);                // e^{-2 pi i i/n} = (cos, -sin)
+        gtab[2 * m + i] = sn;                  // sin(lambda_i) = -sin(2 pi i/n)
+        gtab[2 * m + n + i] = -c;              // cos(lambda_i) = -cos(2 pi i/n)
+    }
+    if (ee == hipSuccess) ee = up(p->gradtab, gtab.data(), gtab.size() * sizeof(double));
     if (ee == hipSuccess) ee = hipStreamSynchronize(stream);
     if (ee != hipSuccess) {
         int r = hip_fail(ee, "uploading plan tables");
@@ -1253,6 +1298,59 @@ extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, do
     const size_t bytes = (size_t)p->n * p->m * sizeof(double);
     if (overlap(f, out, bytes)) return SP_ERR_ALIAS;
     return run_fp64(p, f, out, sp::kTransformOnly, 0.0, true, false, false, (hipStream_t)hip_stream);
+}
+
+// ------------------------------------------------------------ tangential gradient
+extern "C" int sphere_poisson_tangential_gradient(sp_plan p, const double* f, double* gx, double* gy, double* gz,
+                                                  void* hip_stream) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!f || !gx || !gy || !gz) return SP_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
+    const void* bufs[4] = {f, gx, gy, gz};
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b)
+            if (overlap(bufs[a], bufs[b], bytes)) return SP_ERR_ALIAS;
+    if (!p->grad) return SP_ERR_UNSUPPORTED_SIZE;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = p->n, m = p->m, N = p->N;
+    const int rw = 1 << p->rw_log2;
+    // 1. half spectrum of f (weights 1/n) -> spec64
+    sp::LambdaArgs<double> la{};
+    la.x = f; la.spec = p->spec64; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n; la.rowscale = nullptr;
+    la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.lay_log2 = p->lay_log2; la.fft = p->fft_lam;
+    la.nthr = p->lam_threads; la.w_mid = 1.0 / n; la.w_end = 1.0 / n;
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(p->lam_grid), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
+    }
+    // 2. theta derivative of every wavenumber's series -> specB (same run length);
+    // 3. then each series divided by sin(theta), in place (every workgroup reads
+    //    its whole column part before writing it)
+    sp::ThetaArgs<double> ta{};
+    ta.spec = p->spec64; ta.spec_out = p->specB; ta.tw = p->t64.pass_m; ta.eq = p->t64.eq; ta.ws = p->t64.ws;
+    ta.n = n; ta.m = m; ta.N = N; ta.lay_log2 = p->lay_log2; ta.lay_out_log2 = p->lay_log2;
+    ta.fft = p->fft_theta; ta.nthr_fft = p->theta_fft_threads; ta.mode = sp::kDerivative; ta.k8 = p->k8;
+    ta.c0 = 0.0; ta.k0tab = p->k0tab; ta.fint_w = nullptr; ta.fint_out = p->scal;
+    for (int mode : {(int)sp::kDerivative, (int)sp::kDivideSin}) {
+        ta.mode = mode;
+        ta.spec_out = mode == sp::kDerivative ? p->specB : p->spec64;
+        ProfScope ps(p, SP_KERNEL_THETA, s);
+        hipLaunchKernelGGL(p->theta_real ? p->kd.theta_real : p->kd.theta, dim3(p->theta_grid),
+                           dim3(p->theta_threads), p->theta_lds64, s, ta);
+    }
+    // 4. both inverse lambda transforms per row, combined into the three components
+    sp::GradArgs ga{};
+    ga.spec_q = p->spec64; ga.spec_t = p->specB; ga.gx = gx; ga.gy = gy; ga.gz = gz;
+    ga.tw = p->t64.tw_n; ga.ptw = p->t64.pass_n; ga.rowtab = p->gradtab; ga.coltab = p->gradtab + 2 * (size_t)m;
+    ga.n = n; ga.m = m; ga.N = N; ga.rw_log2 = p->grad_rw_log2; ga.lay_log2 = p->lay_log2;
+    ga.fft = p->fft_lam; ga.nthr = p->lam_threads;
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_GRAD, s);
+        hipLaunchKernelGGL(p->grad, dim3(p->grad_grid), dim3(p->grad_block), p->grad_lds, s, ga);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
 }
 
 // ------------------------------------------------------------ batches
