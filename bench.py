@@ -274,7 +274,7 @@ def bench_gradient(args, P, torch, n, m):
         plan.tangential_gradient(f, outs=outs)
     torch.cuda.synchronize()
     steps = max(1, args.steps // 2)
-    plan.profile_enable(3 * steps)
+    plan.profile_enable(4 * steps)   # four launches per call: lambda forward, two theta passes, gradient
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
