@@ -172,6 +172,27 @@ const char* sphere_poisson_strerror(int code);
 int sphere_poisson_tangential_gradient(sp_plan plan, const double* f, double* gx, double* gy, double* gz,
                                        void* hip_stream);
 
+/* Vector calculus on the sphere (Section 4, Vector calculus), built on the
+ * tangential derivatives above; p = (x, y, z) is the point of the unit
+ * sphere and n = p its outward normal.  Vector fields are given by their
+ * three Cartesian components (fx, fy, fz), each a device [m][n] float64 grid
+ * function; outputs likewise.  Outputs must not overlap each other or any
+ * input (SP_ERR_ALIAS).  Same precision, stream, workspace and error rules as
+ * sphere_poisson_tangential_gradient.
+ *   curl_scalar: (ux, uy, uz) = n x grad f            (eq. CurlScalarF)
+ *   divergence:  out = d^t fx/dx + d^t fy/dy + d^t fz/dz
+ *   curl:        (cx, cy, cz) = (d^t fz/dy - d^t fy/dz, d^t fx/dz - d^t fz/dx, d^t fy/dx - d^t fx/dy)
+ *   vorticity:   out = n . curl(f)
+ * divergence, curl and vorticity run the derivative passes once per component. */
+int sphere_poisson_curl_scalar(sp_plan plan, const double* f, double* ux, double* uy, double* uz,
+                               void* hip_stream);
+int sphere_poisson_divergence(sp_plan plan, const double* fx, const double* fy, const double* fz, double* out,
+                              void* hip_stream);
+int sphere_poisson_curl(sp_plan plan, const double* fx, const double* fy, const double* fz, double* cx,
+                        double* cy, double* cz, void* hip_stream);
+int sphere_poisson_vorticity(sp_plan plan, const double* fx, const double* fy, const double* fz, double* out,
+                             void* hip_stream);
+
 /* Bytes of device workspace a plan for `desc` would allocate (0 on invalid desc). */
 size_t sphere_poisson_workspace_bytes(const sp_desc* desc);
 

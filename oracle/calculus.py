@@ -34,7 +34,8 @@ import numpy as np
 
 from .sphere_poisson import coeffs2, dfs_double, lambda_grid, theta_grid
 
-__all__ = ["msin_matrix", "tangential_gradient", "polynomial_surface_gradient"]
+__all__ = ["msin_matrix", "tangential_gradient", "polynomial_surface_gradient", "curl_scalar", "divergence",
+           "curl", "vorticity"]
 
 
 def msin_matrix(M: int) -> np.ndarray:
@@ -132,3 +133,34 @@ def polynomial_surface_gradient(grad_F, m: int, n: int):
     Fx, Fy, Fz = (np.broadcast_to(v, x.shape) for v in grad_F(x, y, z))
     radial = x * Fx + y * Fy + z * Fz
     return Fx - radial * x, Fy - radial * y, Fz - radial * z
+
+
+def _point(m: int, n: int):
+    th = theta_grid(m)[:, None]
+    lam = lambda_grid(n)[None, :]
+    return np.cos(lam) * np.sin(th), np.sin(lam) * np.sin(th), np.cos(th) * np.ones_like(lam)
+
+
+def curl_scalar(f: np.ndarray):
+    """n x grad f with n = p = (x, y, z) (Section 4, eq. CurlScalarF)."""
+    gx, gy, gz = tangential_gradient(f)
+    x, y, z = _point(*f.shape)
+    return y * gz - z * gy, z * gx - x * gz, x * gy - y * gx
+
+
+def divergence(fx: np.ndarray, fy: np.ndarray, fz: np.ndarray) -> np.ndarray:
+    """d^t fx/dx + d^t fy/dy + d^t fz/dz (Section 4, Vector calculus)."""
+    return tangential_gradient(fx)[0] + tangential_gradient(fy)[1] + tangential_gradient(fz)[2]
+
+
+def curl(fx: np.ndarray, fy: np.ndarray, fz: np.ndarray):
+    """(d^t fz/dy - d^t fy/dz, d^t fx/dz - d^t fz/dx, d^t fy/dx - d^t fx/dy)."""
+    gx, gy, gz = tangential_gradient(fx), tangential_gradient(fy), tangential_gradient(fz)
+    return gz[1] - gy[2], gx[2] - gz[0], gy[0] - gx[1]
+
+
+def vorticity(fx: np.ndarray, fy: np.ndarray, fz: np.ndarray) -> np.ndarray:
+    """n . curl f (Section 4, Vector calculus)."""
+    cx, cy, cz = curl(fx, fy, fz)
+    x, y, z = _point(*fx.shape)
+    return x * cx + y * cy + z * cz

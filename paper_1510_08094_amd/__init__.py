@@ -84,11 +84,17 @@ def library():
     lib.sphere_poisson_workspace_bytes.restype = ctypes.c_size_t
     lib.sphere_poisson_transform_roundtrip.argtypes = [vp, vp, vp, vp]
     lib.sphere_poisson_tangential_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_curl_scalar.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_divergence.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_curl.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_vorticity.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sphere_poisson_profile_enable.argtypes = [vp, ci]
     lib.sphere_poisson_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
     for name in ("sphere_poisson_profile_enable", "sphere_poisson_profile_read", "sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
-                 "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient"):
+                 "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
+                 "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
+                 "sphere_poisson_vorticity"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -176,6 +182,34 @@ class SpherePoisson:
                 self._plan, ctypes.c_void_p(f.data_ptr()), *(ctypes.c_void_p(g.data_ptr()) for g in gs),
                 ctypes.c_void_p(_stream_handle(self.device))))
         return tuple(gs)
+
+    def _field_call(self, name, ins, nout, outs):
+        for t in ins:
+            _check_grid(t, self.m, self.n, "input")
+        gs = [torch.empty_like(ins[0]) for _ in range(nout)] if outs is None else list(outs)
+        for g in gs:
+            _check_grid(g, self.m, self.n, "out")
+        with torch.cuda.device(self.device):
+            _check(getattr(library(), name)(
+                self._plan, *(ctypes.c_void_p(t.data_ptr()) for t in ins),
+                *(ctypes.c_void_p(g.data_ptr()) for g in gs), ctypes.c_void_p(_stream_handle(self.device))))
+        return tuple(gs) if nout > 1 else gs[0]
+
+    def curl_scalar(self, f: torch.Tensor, outs=None):
+        """n x grad f (Section 4, eq. CurlScalarF): three components."""
+        return self._field_call("sphere_poisson_curl_scalar", [f], 3, outs)
+
+    def divergence(self, fx, fy, fz, out=None):
+        """Surface divergence of the tangent field (fx, fy, fz)."""
+        return self._field_call("sphere_poisson_divergence", [fx, fy, fz], 1, None if out is None else [out])
+
+    def curl(self, fx, fy, fz, outs=None):
+        """Surface curl of the tangent field (fx, fy, fz): three components."""
+        return self._field_call("sphere_poisson_curl", [fx, fy, fz], 3, outs)
+
+    def vorticity(self, fx, fy, fz, out=None):
+        """n . curl of the tangent field (fx, fy, fz)."""
+        return self._field_call("sphere_poisson_vorticity", [fx, fy, fz], 1, None if out is None else [out])
 
     KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce",
                     "lambda_grad")

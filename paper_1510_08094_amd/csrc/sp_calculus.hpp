@@ -17,12 +17,24 @@
 
 namespace sp {
 
+// What the pass writes from the gradient g of one scalar field f (p = (x, y, z)
+// the point of the unit sphere, n = p its normal; Section 4, Vector calculus):
+//   out_a (+)= sum_b wg[a][b] g_b + wn[a][b] (n x g)_b,   a < nout.
+// The host fills the weights: the gradient (wg = I), the curl of a scalar
+// (eq. CurlScalarF, wn = I), and the terms that component c of a vector field
+// adds to its divergence (wg[0][c] = 1), surface curl (wg[a][b] = eps_abc) and
+// vorticity (wn[0][c] = 1).
+
 struct GradArgs {
     const Cx<double>* spec_q;   // half spectrum of f / sin(theta) (theta pass, divide mode)
     const Cx<double>* spec_t;   // half spectrum of d f / d theta (theta pass, derivative mode)
-    double* gx;                 // outputs [m][n]
+    double* gx;                 // outputs [m][n] (out_0, out_1, out_2; unused ones may be null)
     double* gy;
     double* gz;
+    double wg[3][3];            // output weights on g
+    double wn[3][3];            // output weights on n x g
+    int nout;                   // outputs written (1 or 3)
+    int accumulate;             // 1: add to the outputs instead of writing them
     const Cx<double>* tw;       // e^{-2 pi i t/n}
     const Cx<double>* ptw;      // per-pass twiddles of the length-N DFT
     const double* rowtab;       // per row j: cos(theta_j), sin(theta_j)  ([2][m])
@@ -57,17 +69,40 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
         const double2* sl = reinterpret_cast<const double2*>(a.coltab);
         const double2* cl = reinterpret_cast<const double2*>(a.coltab + a.n);
         double2* ox = reinterpret_cast<double2*>(a.gx + (size_t)j * a.n);
-        double2* oy = reinterpret_cast<double2*>(a.gy + (size_t)j * a.n);
-        double2* oz = reinterpret_cast<double2*>(a.gz + (size_t)j * a.n);
+        double2* oy = a.gy ? reinterpret_cast<double2*>(a.gy + (size_t)j * a.n) : nullptr;
+        double2* oz = a.gz ? reinterpret_cast<double2*>(a.gz + (size_t)j * a.n) : nullptr;
+        const bool acc = a.accumulate != 0;
+        const int nout = a.nout;
         for (int i = t; i < N; i += a.nthr) {
             const Cx<double> dl = fl[i], dt = ft[i];
             const double2 s = sl[i], c = cl[i];
-            // samples 2i (.x) and 2i+1 (.y)
-            const double ax = dl.x, ay = dl.y;
-            const double bx = dt.x * cst, by = dt.y * cst;
-            ox[i] = double2{-s.x * ax + c.x * bx, -s.y * ay + c.y * by};
-            oy[i] = double2{c.x * ax + s.x * bx, c.y * ay + s.y * by};
-            oz[i] = double2{-snt * dt.x, -snt * dt.y};
+            double r[3][2];   // the three outputs at samples 2i, 2i+1
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double sl_ = h ? s.y : s.x, cl_ = h ? c.y : c.x;
+                const double A = h ? dl.y : dl.x, Bt = h ? dt.y : dt.x;
+                const double g[3] = {-sl_ * A + cl_ * cst * Bt,    // d^t/dx
+                                     cl_ * A + sl_ * cst * Bt,     // d^t/dy
+                                     -snt * Bt};                   // d^t/dz
+                const double px = cl_ * snt, py = sl_ * snt, pz = cst;   // the point (and normal)
+                const double nx[3] = {py * g[2] - pz * g[1], pz * g[0] - px * g[2], px * g[1] - py * g[0]};
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) v += a.wg[o][b] * g[b] + a.wn[o][b] * nx[b];
+                    r[o][h] = v;
+                }
+            }
+            double2* outs[3] = {ox, oy, oz};
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                if (o < nout) {
+                    double2 v = double2{r[o][0], r[o][1]};
+                    if (acc) { const double2 w = outs[o][i]; v.x += w.x; v.y += w.y; }
+                    outs[o][i] = v;
+                }
+            }
         }
     }
 }

@@ -1301,17 +1301,38 @@ extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, do
 }
 
 // ------------------------------------------------------------ tangential gradient
-extern "C" int sphere_poisson_tangential_gradient(sp_plan p, const double* f, double* gx, double* gy, double* gz,
-                                                  void* hip_stream) {
-    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
-    if (!f || !gx || !gy || !gz) return SP_ERR_INVALID_ARG;
-    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
-    const void* bufs[4] = {f, gx, gy, gz};
-    for (int a = 0; a < 4; ++a)
-        for (int b = a + 1; b < 4; ++b)
-            if (overlap(bufs[a], bufs[b], bytes)) return SP_ERR_ALIAS;
+namespace {
+
+// What the gradient pass writes from the gradient g of one scalar field
+// (Section 4, Vector calculus): the gradient, n x g (the curl of a scalar),
+// or the term that component c of a vector field adds to its divergence,
+// surface curl or vorticity.
+enum GradOut { kGradient = 0, kNormalCross = 1, kDivTerm = 2, kCurlTerm = 3, kVortTerm = 4 };
+
+void grad_weights(int out_mode, int c, sp::GradArgs& ga) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) { ga.wg[a][b] = 0.0; ga.wn[a][b] = 0.0; }
+    ga.nout = 3;
+    switch (out_mode) {
+        case kGradient: for (int a = 0; a < 3; ++a) ga.wg[a][a] = 1.0; break;
+        case kNormalCross: for (int a = 0; a < 3; ++a) ga.wn[a][a] = 1.0; break;
+        case kDivTerm: ga.wg[0][c] = 1.0; ga.nout = 1; break;
+        case kCurlTerm:   // curl_a = sum_{b} eps_{a b c} d_b f_c
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const int e = (a - b) * (b - c) * (c - a);   // Levi-Civita: +2 / -2 / 0
+                    ga.wg[a][b] = e > 0 ? 1.0 : e < 0 ? -1.0 : 0.0;
+                }
+            break;
+        default: ga.wn[0][c] = 1.0; ga.nout = 1; break;   // kVortTerm: (n x grad f_c)_c
+    }
+}
+
+// The tangential derivatives of one grid function f, written or added
+// (accumulate) as the output mode asks.
+int run_grad(sp_plan p, const double* f, int out_mode, int comp, bool accumulate, double* o0, double* o1,
+             double* o2, hipStream_t s) {
     if (!p->grad) return SP_ERR_UNSUPPORTED_SIZE;
-    hipStream_t s = (hipStream_t)hip_stream;
     const int n = p->n, m = p->m, N = p->N;
     const int rw = 1 << p->rw_log2;
     // 1. half spectrum of f (weights 1/n) -> spec64
@@ -1338,9 +1359,11 @@ extern "C" int sphere_poisson_tangential_gradient(sp_plan p, const double* f, do
         hipLaunchKernelGGL(p->theta_real ? p->kd.theta_real : p->kd.theta, dim3(p->theta_grid),
                            dim3(p->theta_threads), p->theta_lds64, s, ta);
     }
-    // 4. both inverse lambda transforms per row, combined into the three components
+    // 4. both inverse lambda transforms per row, combined into the outputs
     sp::GradArgs ga{};
-    ga.spec_q = p->spec64; ga.spec_t = p->specB; ga.gx = gx; ga.gy = gy; ga.gz = gz;
+    ga.spec_q = p->spec64; ga.spec_t = p->specB; ga.gx = o0; ga.gy = o1; ga.gz = o2;
+    grad_weights(out_mode, comp, ga);
+    ga.accumulate = accumulate ? 1 : 0;
     ga.tw = p->t64.tw_n; ga.ptw = p->t64.pass_n; ga.rowtab = p->gradtab; ga.coltab = p->gradtab + 2 * (size_t)m;
     ga.n = n; ga.m = m; ga.N = N; ga.rw_log2 = p->grad_rw_log2; ga.lay_log2 = p->lay_log2;
     ga.fft = p->fft_lam; ga.nthr = p->lam_threads;
@@ -1351,6 +1374,83 @@ extern "C" int sphere_poisson_tangential_gradient(sp_plan p, const double* f, do
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return SP_OK;
+}
+
+// Argument checks shared by the vector-calculus entry points: every pointer
+// set, and no output overlapping an input or another output.
+int check_fields(sp_plan p, const double* const* in, int nin, double* const* out, int nout) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    for (int a = 0; a < nin; ++a)
+        if (!in[a]) return SP_ERR_INVALID_ARG;
+    for (int a = 0; a < nout; ++a)
+        if (!out[a]) return SP_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)p->n * p->m * sizeof(double);
+    for (int a = 0; a < nout; ++a) {
+        for (int b = 0; b < nin; ++b)
+            if (overlap(out[a], in[b], bytes)) return SP_ERR_ALIAS;
+        for (int b = a + 1; b < nout; ++b)
+            if (overlap(out[a], out[b], bytes)) return SP_ERR_ALIAS;
+    }
+    return p->grad ? SP_OK : SP_ERR_UNSUPPORTED_SIZE;
+}
+
+// A vector field's three components, each through run_grad, the first
+// writing the outputs and the others adding to them.
+int run_vector_op(sp_plan p, const double* const* fc, int mode, double* o0, double* o1, double* o2,
+                  hipStream_t s) {
+    for (int c = 0; c < 3; ++c) {
+        const int st = run_grad(p, fc[c], mode, c, c > 0, o0, o1, o2, s);
+        if (st != SP_OK) return st;
+    }
+    return SP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ tangential derivatives and vector calculus
+extern "C" int sphere_poisson_tangential_gradient(sp_plan p, const double* f, double* gx, double* gy, double* gz,
+                                                  void* hip_stream) {
+    const double* in[1] = {f};
+    double* out[3] = {gx, gy, gz};
+    const int st = check_fields(p, in, 1, out, 3);
+    if (st != SP_OK) return st;
+    return run_grad(p, f, kGradient, 0, false, gx, gy, gz, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_curl_scalar(sp_plan p, const double* f, double* ux, double* uy, double* uz,
+                                          void* hip_stream) {
+    const double* in[1] = {f};
+    double* out[3] = {ux, uy, uz};
+    const int st = check_fields(p, in, 1, out, 3);
+    if (st != SP_OK) return st;
+    return run_grad(p, f, kNormalCross, 0, false, ux, uy, uz, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_divergence(sp_plan p, const double* fx, const double* fy, const double* fz,
+                                         double* out, void* hip_stream) {
+    const double* in[3] = {fx, fy, fz};
+    double* outs[1] = {out};
+    const int st = check_fields(p, in, 3, outs, 1);
+    if (st != SP_OK) return st;
+    return run_vector_op(p, in, kDivTerm, out, nullptr, nullptr, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_curl(sp_plan p, const double* fx, const double* fy, const double* fz, double* cx,
+                                   double* cy, double* cz, void* hip_stream) {
+    const double* in[3] = {fx, fy, fz};
+    double* outs[3] = {cx, cy, cz};
+    const int st = check_fields(p, in, 3, outs, 3);
+    if (st != SP_OK) return st;
+    return run_vector_op(p, in, kCurlTerm, cx, cy, cz, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_vorticity(sp_plan p, const double* fx, const double* fy, const double* fz,
+                                        double* out, void* hip_stream) {
+    const double* in[3] = {fx, fy, fz};
+    double* outs[1] = {out};
+    const int st = check_fields(p, in, 3, outs, 1);
+    if (st != SP_OK) return st;
+    return run_vector_op(p, in, kVortTerm, out, nullptr, nullptr, (hipStream_t)hip_stream);
 }
 
 // ------------------------------------------------------------ batches

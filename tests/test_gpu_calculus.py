@@ -151,3 +151,78 @@ def test_gradient_errors(P):
         plan.tangential_gradient(f, outs=(a, a, b))
     assert e.value.code == 6
     plan.close()
+
+
+def tol2(n, m):
+    """Two spectral differentiations in a row (e.g. vorticity of n x grad):
+    the rounding floor is amplified twice by the gain of one."""
+    k = max(n // 2, m) * np.sqrt(m)
+    return max(1e-11, np.finfo(np.float64).eps * k * k)
+
+
+def _plan_call(P, n, m, name, *args):
+    plan = P.SpherePoisson(n, m, "fp64")
+    try:
+        res = getattr(plan, name)(*[gpu(a) for a in args])
+        return tuple(host(r) for r in res) if isinstance(res, tuple) else host(res)
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("n,m", [(64, 64), (40, 21), (96, 60), (128, 130)])
+def test_vector_calculus_matches_oracle(P, n, m):
+    print("vector calculus", n, m, flush=True)
+    L = max(1, min(n // 2 - 2, m - 3, 20))
+    fx, fy, fz = (S.sphere_field(61 + c, 0, n, m, L) for c in range(3))
+    assert rel3(_plan_call(P, n, m, "curl_scalar", fx), O.curl_scalar(fx)) <= tol(n, m)
+    assert rel2(_plan_call(P, n, m, "divergence", fx, fy, fz), O.divergence(fx, fy, fz)) <= tol(n, m)
+    assert rel3(_plan_call(P, n, m, "curl", fx, fy, fz), O.curl(fx, fy, fz)) <= tol(n, m)
+    assert rel2(_plan_call(P, n, m, "vorticity", fx, fy, fz), O.vorticity(fx, fy, fz)) <= tol(n, m)
+
+
+@pytest.mark.parametrize("n,m", [(256, 200), (1024, 512)])
+def test_laplacian_identities(P, n, m):
+    """div grad u = f and vort(n x grad u) = f for the generator's pairs
+    (Delta u = f), all on the GPU."""
+    print("identities", n, m, flush=True)
+    f, u = S.sphere_field(53, 0, n, m, min(n, m) // 8, with_solution=True)
+    plan = P.SpherePoisson(n, m, "fp64")
+    ug = gpu(u)
+    g = plan.tangential_gradient(ug)
+    r = plan.curl_scalar(ug)
+    d = host(plan.divergence(*g))
+    v = host(plan.vorticity(*r))
+    plan.close()
+    assert rel2(d, f) <= tol2(n, m)
+    assert rel2(v, f) <= tol2(n, m)
+
+
+def test_rossby_haurwitz_vorticity(P):
+    """Section 4's example at 10^6 samples: u = n x grad psi for
+    psi = cos(theta) + sin(theta)^4 cos(theta) cos(4 lambda); its vorticity is
+    Delta psi = -2 cos(theta) - 30 sin(theta)^4 cos(theta) cos(4 lambda)."""
+    n = m = 1024
+    th = O.theta_grid(m)[:, None]
+    lam = O.lambda_grid(n)[None, :]
+    psi = np.cos(th) + np.sin(th) ** 4 * np.cos(th) * np.cos(4 * lam)
+    lap = -2 * np.cos(th) - 30 * np.sin(th) ** 4 * np.cos(th) * np.cos(4 * lam)
+    plan = P.SpherePoisson(n, m, "fp64")
+    u = plan.curl_scalar(gpu(psi))
+    v = host(plan.vorticity(*u))
+    plan.close()
+    err = rel2(v, lap)
+    print("rossby-haurwitz vorticity rel err", err, flush=True)
+    assert err <= tol2(n, m)
+
+
+def test_vector_calculus_errors(P):
+    f = gpu(np.zeros((32, 32)))
+    a, b = torch.empty_like(f), torch.empty_like(f)
+    plan = P.SpherePoisson(32, 32, "fp64")
+    with pytest.raises(P.SpError) as e:
+        plan.divergence(f, a, b, out=a)
+    assert e.value.code == 6
+    with pytest.raises(P.SpError) as e:
+        plan.curl(f, a, b, outs=(f, torch.empty_like(f), torch.empty_like(f)))
+    assert e.value.code == 6
+    plan.close()

@@ -120,3 +120,50 @@ def test_refined_grid_agrees_on_common_rows():
     a = O.tangential_gradient(S.sphere_field(41, 0, n, m, L))
     b = O.tangential_gradient(S.sphere_field(41, 0, n, 3 * m, L))
     assert _rel3(a, tuple(c[1::3] for c in b)) <= 1e-13
+
+
+def _tol2(n, m):
+    """Two spectral differentiations: the rounding floor eps |f| of the
+    transforms is amplified twice by the gain of one (max(n/2, m) sqrt(m))."""
+    k = max(n // 2, m) * np.sqrt(m)
+    return max(1e-11, np.finfo(np.float64).eps * k * k)
+
+
+@pytest.mark.parametrize("n,m,L", [(48, 40, 10), (64, 33, 12)])
+def test_vector_identities_on_poisson_pairs(n, m, L):
+    """For the generator's pairs (Delta u = f): div grad u = f and
+    vort(n x grad u) = f (both are the surface Laplacian); vort grad u = 0 and
+    div(n x grad u) = 0."""
+    f, u = S.sphere_field(51, 0, n, m, L, with_solution=True)
+    g = O.tangential_gradient(u)
+    r = O.curl_scalar(u)
+    tol = _tol2(n, m)
+    scale = np.max(np.abs(f))
+    assert rel2(O.divergence(*g), f) <= tol
+    assert rel2(O.vorticity(*r), f) <= tol
+    assert np.max(np.abs(O.vorticity(*g))) <= tol * scale
+    assert np.max(np.abs(O.divergence(*r))) <= tol * scale
+
+
+def test_rossby_haurwitz_vorticity():
+    """Section 4's example: u = n x grad psi for the Rossby-Haurwitz stream
+    function psi = cos(theta) + sin(theta)^4 cos(theta) cos(4 lambda), a sum of
+    a degree-1 and a degree-5 harmonic, so vort u = Delta psi
+    = -2 cos(theta) - 30 sin(theta)^4 cos(theta) cos(4 lambda)."""
+    n, m = 64, 48
+    th = O.theta_grid(m)[:, None]
+    lam = O.lambda_grid(n)[None, :]
+    psi = np.cos(th) + np.sin(th) ** 4 * np.cos(th) * np.cos(4 * lam)
+    lap = -2 * np.cos(th) - 30 * np.sin(th) ** 4 * np.cos(th) * np.cos(4 * lam)
+    assert rel2(O.vorticity(*O.curl_scalar(psi)), lap) <= _tol2(n, m)
+
+
+def test_curl_components_against_definition():
+    """The surface curl of a gradient field is tangent (n . curl is the
+    vorticity, zero here) and its components follow the paper's formula."""
+    n, m = 32, 24
+    f = S.sphere_field(52, 0, n, m, 8)
+    gx, gy, gz = O.tangential_gradient(f)
+    cx, cy, cz = O.curl(gx, gy, gz)
+    x, y, z = _grid_xyz(m, n)
+    assert np.max(np.abs(x * cx + y * cy + z * cz)) <= _tol2(n, m) * np.max(np.abs(f))
