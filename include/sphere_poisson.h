@@ -193,6 +193,17 @@ int sphere_poisson_curl(sp_plan plan, const double* fx, const double* fy, const 
 int sphere_poisson_vorticity(sp_plan plan, const double* fx, const double* fy, const double* fz, double* out,
                              void* hip_stream);
 
+/* Integral of a grid function over the unit sphere (Section 4,
+ * "Integration", the sum2 example): 2 pi times the theta quadrature, against
+ * sin(theta), of the row means, with weights exact for cosine series of
+ * degree < m on the half-shifted nodes (exact for band-limited f).
+ * f: input, device [m][n] float64; out: device pointer to one float64,
+ * written asynchronously on `hip_stream`.  The summation order is fixed
+ * (reproducible results).  Uses the plan's workspace: calls on one plan must
+ * not overlap.  Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG, SP_ERR_ALIAS,
+ * SP_ERR_HIP. */
+int sphere_poisson_integral(sp_plan plan, const double* f, double* out, void* hip_stream);
+
 /* Bytes of device workspace a plan for `desc` would allocate (0 on invalid desc). */
 size_t sphere_poisson_workspace_bytes(const sp_desc* desc);
 

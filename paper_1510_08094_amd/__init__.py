@@ -88,13 +88,14 @@ def library():
     lib.sphere_poisson_divergence.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sphere_poisson_curl.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sphere_poisson_vorticity.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_integral.argtypes = [vp, vp, vp, vp]
     lib.sphere_poisson_profile_enable.argtypes = [vp, ci]
     lib.sphere_poisson_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
     for name in ("sphere_poisson_profile_enable", "sphere_poisson_profile_read", "sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
-                 "sphere_poisson_vorticity"):
+                 "sphere_poisson_vorticity", "sphere_poisson_integral"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -194,6 +195,17 @@ class SpherePoisson:
                 self._plan, *(ctypes.c_void_p(t.data_ptr()) for t in ins),
                 *(ctypes.c_void_p(g.data_ptr()) for g in gs), ctypes.c_void_p(_stream_handle(self.device))))
         return tuple(gs) if nout > 1 else gs[0]
+
+    def integral(self, f: torch.Tensor) -> torch.Tensor:
+        """Integral of f over the sphere (Section 4, Integration): a 0-d
+        float64 tensor on f's device, written asynchronously."""
+        _check_grid(f, self.m, self.n, "f")
+        out = torch.empty((), dtype=torch.float64, device=f.device)
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_integral(self._plan, ctypes.c_void_p(f.data_ptr()),
+                                                     ctypes.c_void_p(out.data_ptr()),
+                                                     ctypes.c_void_p(_stream_handle(self.device))))
+        return out
 
     def curl_scalar(self, f: torch.Tensor, outs=None):
         """n x grad f (Section 4, eq. CurlScalarF): three components."""

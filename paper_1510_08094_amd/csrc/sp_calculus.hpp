@@ -115,4 +115,39 @@ __global__ void __launch_bounds__(1024) k_lambda_grad(GradArgs a) {
     lambda_grad_body<EPT, RMAX>(a, jb, smem_raw);
 }
 
+// ---------------------------------------------------------------- integration
+// Integral of f over the sphere (Section 4, "Integration", the sum2
+// command): the lambda integral of row j is 2 pi times its mean, and the
+// theta integral against sin(theta) uses weights W_j exact for cosine
+// series of degree < m on the half-shifted nodes:
+//   int f dS = sum_j W_j (2 pi / n) sum_i f[j][i]   (w[j] = 2 pi W_j / n).
+// First pass: workgroup b sums rows b, b + G, ... (a fixed order, so the
+// result is reproducible) into partial[b]; second pass: one workgroup adds
+// the partials.
+__global__ void __launch_bounds__(256) k_integral_rows(const double* __restrict__ f, const double* __restrict__ w,
+                                                       int n, int m, double* __restrict__ partial) {
+    __shared__ Cx<double> red[8];
+    double acc = 0.0;
+    for (int j = blockIdx.x; j < m; j += gridDim.x) {
+        const double2* row = reinterpret_cast<const double2*>(f + (size_t)j * n);
+        double srow = 0.0;
+        for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+            const double2 v = row[i];
+            srow += v.x + v.y;
+        }
+        acc += srow * w[j];
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_integral_total(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+    __shared__ Cx<double> red[8];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[b];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
 }  // namespace sp

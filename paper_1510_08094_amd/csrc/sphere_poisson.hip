@@ -259,6 +259,8 @@ struct sp_plan_s {
     int grad_rw_log2 = 0, grad_grid = 0, grad_block = 0;
     size_t grad_lds = 0;
     double* gradtab = nullptr;   // [2][m] cos(theta), sin(theta); then [2][n] sin(lambda), cos(lambda)
+    double* intw = nullptr;      // [m] integration weights 2 pi W_j / n (sphere_poisson_integral)
+    double* intpart = nullptr;   // [kIntegralBlocks] partial sums
     // device memory
     void* block = nullptr;    // one allocation holding everything below
     size_t block_bytes = 0;
@@ -319,9 +321,11 @@ struct Layout {
     size_t off_ws64, off_ws32;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
     size_t off_specB, off_spec0, off_specd, off_partial, off_fco;
-    size_t off_grad;
+    size_t off_grad, off_intw, off_intpart;
     size_t spec_elems;
 };
+
+constexpr int kIntegralBlocks = 512;   // workgroups of the first integration pass
 
 // rw: rows per lambda workgroup; rl: spectrum run length (rows), a multiple of rw
 Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
@@ -347,6 +351,8 @@ Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
     L.off_fint = take((size_t)m * sizeof(double));
     L.off_scal = take(16 * sizeof(double));
     L.off_grad = take((size_t)(2 * m + 2 * n) * sizeof(double));
+    L.off_intw = take((size_t)m * sizeof(double));
+    L.off_intpart = take((size_t)kIntegralBlocks * sizeof(double));
     // second float64 spectrum: the theta output of the float64 path (lambda
     // read layout), and in mixed plans the spectrum of the current iterate
     L.off_specB = take(L.spec_elems * sizeof(Cx<double>));
@@ -634,6 +640,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     p->fint_w = (double*)(b + L.off_fint);
     p->scal = (double*)(b + L.off_scal);
     p->gradtab = (double*)(b + L.off_grad);
+    p->intw = (double*)(b + L.off_intw);
+    p->intpart = (double*)(b + L.off_intpart);
     p->specB = (Cx<double>*)(b + L.off_specB);
     if (mixed) {
         p->spec0 = (Cx<float>*)(b + L.off_spec0);
@@ -688,6 +696,11 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         gtab[2 * m + n + i] = -c;              // cos(lambda_i) = -cos(2 pi i/n)
     }
     if (ee == hipSuccess) ee = up(p->gradtab, gtab.data(), gtab.size() * sizeof(double));
+    // integration: fint_w holds 2 pi W_j / sin^2(theta_j) (it is applied to the
+    // spectrum of sin^2 f); the grid integral needs 2 pi W_j / n
+    std::vector<double> intw(m);
+    for (int j = 0; j < m; ++j) intw[j] = fint[j] * sin2[j] / n;
+    if (ee == hipSuccess) ee = up(p->intw, intw.data(), intw.size() * sizeof(double));
     if (ee == hipSuccess) ee = hipStreamSynchronize(stream);
     if (ee != hipSuccess) {
         int r = hip_fail(ee, "uploading plan tables");
@@ -1451,6 +1464,21 @@ extern "C" int sphere_poisson_vorticity(sp_plan p, const double* fx, const doubl
     const int st = check_fields(p, in, 3, outs, 1);
     if (st != SP_OK) return st;
     return run_vector_op(p, in, kVortTerm, out, nullptr, nullptr, (hipStream_t)hip_stream);
+}
+
+// ------------------------------------------------------------ integration
+extern "C" int sphere_poisson_integral(sp_plan p, const double* f, double* out, void* hip_stream) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!f || !out) return SP_ERR_INVALID_ARG;
+    if (overlap(f, out, (size_t)p->n * p->m * sizeof(double))) return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nb = std::min(p->m, kIntegralBlocks);
+    hipLaunchKernelGGL(sp::k_integral_rows, dim3(nb), dim3(256), 0, s, f, (const double*)p->intw, p->n, p->m,
+                       p->intpart);
+    hipLaunchKernelGGL(sp::k_integral_total, dim3(1), dim3(256), 0, s, (const double*)p->intpart, nb, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
 }
 
 // ------------------------------------------------------------ batches

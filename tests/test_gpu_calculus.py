@@ -226,3 +226,42 @@ def test_vector_calculus_errors(P):
         plan.curl(f, a, b, outs=(f, torch.empty_like(f), torch.empty_like(f)))
     assert e.value.code == 6
     plan.close()
+
+
+def _sum2_integrand(m, n):
+    x, y, z = grid_xyz(m, n)
+    return 1 + x + y ** 2 + x ** 2 * y + x ** 4 + y ** 5 + (x * y * z) ** 2
+
+
+@pytest.mark.parametrize("n,m", [(32, 24), (64, 48), (10000, 10000)])
+def test_integral_paper_example(P, n, m):
+    """Section 4's sum2 example: the integral of 1 + x + y^2 + x^2 y + x^4 + y^5
+    + (x y z)^2 over the sphere is 216 pi / 35 (the paper prints
+    19.388114662154155); tests/golden/sum2_example.json holds the citation."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sum2_example.json")))
+    f = _sum2_integrand(m, n)
+    plan = P.SpherePoisson(n, m, "fp64")
+    v = float(plan.integral(gpu(f)).cpu())
+    plan.close()
+    exact = 216 * np.pi / 35
+    assert abs(v - exact) <= (1e-13 if n * m < 10 ** 6 else 1e-11) * exact
+    assert abs(g["paper_printed_value"] - exact) <= 1e-14
+
+
+@pytest.mark.parametrize("n,m", [(64, 64), (40, 21), (150, 75), (256, 200)])
+def test_integral_matches_oracle(P, n, m):
+    f = S.sphere_field(71, 0, n, m, min(n // 2 - 2, m - 3, 30)) + 0.75
+    plan = P.SpherePoisson(n, m, "mixed")
+    v = float(plan.integral(gpu(f)).cpu())
+    plan.close()
+    ref = O.sum2(f)
+    assert abs(v - ref) <= 1e-13 * abs(ref)
+
+
+def test_integral_errors(P):
+    f = gpu(np.zeros((16, 16)))
+    plan = P.SpherePoisson(16, 16, "fp64")
+    out = plan.integral(f)
+    assert float(out.cpu()) == 0.0
+    plan.close()
