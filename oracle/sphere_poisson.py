@@ -33,7 +33,7 @@ import scipy.sparse.linalg as spla
 __all__ = [
     "lambda_grid", "theta_grid", "doubled_theta_grid", "dfs_double",
     "coeffs2", "sample2", "coefficient_operators", "sylvester_operator",
-    "integration_weights", "sum2", "solve_literal",
+    "integration_weights", "sum2", "solve_literal", "solve_coefficients",
     "cos_analysis", "cos_synthesis", "sin_analysis", "sin_synthesis",
     "reduced_bands", "thomas", "solve_reduced", "adjoint_reduced",
     "dense_operator", "surface_integral",
@@ -189,18 +189,28 @@ def solve_literal(f: np.ndarray, integral: float = 0.0, transform: str = "auto",
     """Poisson on the sphere, Section 5, step by step:
     1. double f (eq. BMCsphere) and scale the samples by sin(theta)^2;
     2. take the 2D Fourier coefficients F (eq. tildeuFourierExpansion);
-    3. for each k != 0 solve (L - k^2 I) X_k = F_k (eq. linearSystems, sign
-       as read from the Sylvester equation);
-    4. for k = 0 replace row q = 0 by w^T with right-hand side c/(2 pi)
-       (eq. pentdiagonalPlusRankOne with a prescribed integral c);
+    3.-4. solve for the coefficients of u (``solve_coefficients``);
     5. evaluate sum X_{qk} e^{iq theta} e^{ik lambda} on the original rows.
     ``solver='dense'`` uses LU on the full matrices, ``'banded'`` a sparse
     direct solve of the same matrices."""
     m, n = f.shape
-    mp = 2 * m
     th2 = doubled_theta_grid(m)
     bt = np.sin(th2)[:, None] ** 2 * dfs_double(f)
     F = coeffs2(bt, transform)
+    X = solve_coefficients(F, integral, solver)
+    u = sample2(X, theta_grid(m), n, transform)
+    return np.real(u)
+
+
+def solve_coefficients(F: np.ndarray, integral: float = 0.0, solver: str = "auto") -> np.ndarray:
+    """Steps 3-4 of Section 5 on the coefficient matrix F of sin(theta)^2 f~
+    ([2m, n], q = -m..m-1 rows, k = -n/2..n/2-1 columns):
+    3. for each k != 0 solve (L - k^2 I) X_k = F_k (eq. linearSystems, sign
+       as read from the Sylvester equation);
+    4. for k = 0 replace row q = 0 by w^T with right-hand side c/(2 pi)
+       (eq. pentdiagonalPlusRankOne with a prescribed integral c).
+    Returns the coefficient matrix X of u~."""
+    mp, n = F.shape
     qs, ks = _mode_ranges(mp, n)
     if solver == "auto":
         solver = "dense" if mp <= 256 else "banded"
@@ -226,8 +236,7 @@ def solve_literal(f: np.ndarray, integral: float = 0.0, transform: str = "auto",
             X[:, ci] = spla.spsolve(sp.csc_matrix(A), rhs)
         else:
             X[:, ci] = np.linalg.solve(A, rhs)
-    u = sample2(X, theta_grid(m), n, transform)
-    return np.real(u)
+    return X
 
 
 # ----------------------------------------------------------------------------

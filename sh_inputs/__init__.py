@@ -15,7 +15,13 @@ Coefficients are drawn as c_lM = z / (1 + l)^2 with z ~ N(0, 1), l = 1..L,
 in the order l ascending, then M = -l..l, from
 ``numpy.random.default_rng([cfg, rhs, tag])``; tags: 0 = coefficients of f,
 1 = coefficients of an observed field, 2 = noise, 3 = a finite-difference
-direction, 4 = grid sizes.
+direction, 4 = grid sizes, 5 = low-rank factors.
+
+Right-hand sides in low-rank form, f(lambda, theta) = sum_j d_j c_j(theta)
+r_j(lambda): ``sphere_field_factors`` writes a band-limited field as its
+2L + 1 (theta profile, lambda mode) pairs; ``lowrank_factors`` draws
+d_j = z_j 2^-j and random trigonometric polynomials of degree <= L with
+coefficients z / (1 + l)^2.
 """
 from __future__ import annotations
 
@@ -32,7 +38,7 @@ _SO = os.path.join(_HERE, "libshsynth.so")
 _lock = threading.Lock()
 _handle = None
 
-TAG_F, TAG_OBS, TAG_NOISE, TAG_DIR, TAG_SIZES = 0, 1, 2, 3, 4
+TAG_F, TAG_OBS, TAG_NOISE, TAG_DIR, TAG_SIZES, TAG_LOWRANK = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> str:
@@ -157,3 +163,37 @@ def cartesian(n: int, m: int):
     lam, th = grid(n, m)
     L, T = np.meshgrid(lam, th)
     return np.cos(L) * np.sin(T), np.sin(L) * np.sin(T), np.cos(T)
+
+
+def lowrank_factors(cfg: int, rhs: int, n: int, m: int, K: int, L: int):
+    """(d [K], C [K, m], R [K, n]): C[j, t] = c_j(theta_t), R[j, i] = r_j(lambda_i),
+    random trigonometric polynomials of degree <= L (cos and sin terms).  The
+    product need not be smooth at the poles: these exercise the arithmetic of
+    a low-rank right-hand side, not the regularity of a field on the sphere."""
+    rng = np.random.default_rng([cfg, rhs, TAG_LOWRANK])
+    lam, th = grid(n, m)
+    d = rng.standard_normal(K) * 2.0 ** -np.arange(K)
+    l = np.arange(L + 1)
+    w = 1.0 / (1.0 + l) ** 2
+    ac, bc, ar, br = (rng.standard_normal((K, L + 1)) * w for _ in range(4))
+    C = ac @ np.cos(np.outer(l, th)) + bc @ np.sin(np.outer(l, th))
+    R = ar @ np.cos(np.outer(l, lam)) + br @ np.sin(np.outer(l, lam))
+    return d, C, R
+
+
+def sphere_field_factors(cfg: int, rhs: int, n: int, m: int, L: int, tag: int = TAG_F,
+                         with_solution: bool = False):
+    """The seeded band-limited field of ``sphere_field`` in low-rank form:
+    f = sum_{M=0}^{L} A_M(theta) cos(M lambda) + sum_{M=1}^{L} B_M(theta) sin(M lambda),
+    rank K = 2L + 1, d = 1.  Returns (d, C, R) and optionally the exact
+    zero-mean solution of Delta u = f on the grid."""
+    c = draw_coeffs(L, [cfg, rhs, tag])
+    A, B = legendre_sums(m, L, [c])
+    lam, _ = grid(n, m)
+    M = np.arange(L + 1)
+    C = np.vstack([A[0], B[0, 1:]])
+    R = np.vstack([np.cos(np.outer(M, lam)), np.sin(np.outer(M[1:], lam))])
+    d = np.ones(2 * L + 1)
+    if with_solution:
+        return d, C, R, synth(n, m, L, [laplacian_inverse_coeffs(c, L)])[0]
+    return d, C, R
