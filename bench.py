@@ -33,8 +33,9 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
-    """Algorithmic HBM bytes of one launch (what the kernel must read and write)."""
+def kernel_bytes(kind: str, n: int, m: int, precision: str, rank: int = 0) -> int:
+    """Algorithmic HBM bytes of one launch (what the kernel must read and write);
+    `rank`: the low-rank right-hand side's K (its two kernels)."""
     N = n // 2
     spec64 = m * (N + 1) * 16
     spec32 = m * (N + 1) * 8
@@ -53,6 +54,10 @@ def kernel_bytes(kind: str, n: int, m: int, precision: str) -> int:
         "lambda_upd": grid // 2 + spec32 + grid,
         # tangential gradient: both float64 spectra read, three components written
         "lambda_grad": 2 * spec64 + 3 * grid,
+        # low-rank right-hand side: the factors' half spectra (K rows of r in, K spectra out),
+        # then the rank-K product (c, those spectra and sin^2 in, the float64 spectrum out)
+        "lowrank_rows": rank * n * 8 + rank * (N + 1) * 16,
+        "lowrank": rank * m * 8 + rank * (N + 1) * 16 + m * 8 + spec64,
     }
     return table[kind]
 
@@ -107,6 +112,7 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
     ap.add_argument("--no-gradient", action="store_true", help="skip the tangential-gradient measurement")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank right-hand side measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 800 MB device-to-device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -231,6 +237,8 @@ def main():
     del fg, ug
     if not args.no_gradient:
         out["gradient"] = bench_gradient(args, P, torch, n, m)
+    if not args.no_lowrank:
+        out["lowrank"] = bench_lowrank(args, P, S, torch, np, n, m)
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
@@ -303,6 +311,51 @@ def bench_gradient(args, P, torch, n, m):
     return {"workload": "tangential_gradient_n%d_m%d_fp64" % (n, m), "ms_per_call": ms,
             "dof_per_s": n * m / (ms * 1e-3), "alg_bytes_per_dof": 72, "kernels": kern,
             "rel_err_vs_closed_form": float(err)}
+
+
+def bench_lowrank(args, P, S, torch, np, n, m, L=12):
+    """Solve with the right-hand side given in low-rank form (rank K = 2L + 1:
+    a band-limited field as its theta-profile / lambda-mode factors), both
+    precisions: time per solve with the factors resident, library HIP-event
+    kernel times, error against the closed-form solution on every 97th row."""
+    K = 2 * L + 1
+    d, C, R, u_exact = S.sphere_field_factors(21, 0, n, m, L, with_solution=True)
+    dg, Cg, Rg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (d, C, R))
+    rows = np.arange(0, m, 97)
+    res = {"workload": "lowrank_rhs_rank%d_n%d_m%d" % (K, n, m), "rank": K}
+    for prec in ("mixed", "fp64"):
+        plan = P.SpherePoisson(n, m, prec)
+        u = torch.empty((m, n), dtype=torch.float64, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            plan.solve_lowrank(dg, Cg, Rg, out=u)
+        torch.cuda.synchronize()
+        steps = max(1, args.steps // 2)
+        plan.profile_enable(8 * steps)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            plan.solve_lowrank(dg, Cg, Rg, out=u)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        prof = plan.profile_read()
+        plan.profile_enable(0)
+        uh = u[torch.from_numpy(rows).cuda()].cpu().numpy()
+        err = float(np.linalg.norm(uh - u_exact[rows]) / np.linalg.norm(u_exact[rows]))
+        kern = {}
+        for k, (tot, cnt) in prof.items():
+            name = "lowrank_rows" if k == "lambda_fwd" else k
+            alg = kernel_bytes(name, n, m, prec, rank=K)
+            avg = tot / cnt
+            kern[name] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": alg,
+                          "alg_GBps": round(alg / (avg * 1e-3) / 1e9, 1)}
+        plan.close()
+        del u
+        log("bench: lowrank %s %.3f ms/solve, %.3e DOF/s, rel err %.2e" % (prec, ms, n * m / (ms * 1e-3), err))
+        res[prec] = {"ms_per_solve": ms, "dof_per_s": n * m / (ms * 1e-3), "kernels": kern,
+                     "rel_err_vs_closed_form": err}
+    return res
 
 
 def bench_batch(args, P, S, torch, np):

@@ -123,6 +123,25 @@ int sphere_poisson_plan(sp_plan* out, const sp_desc* desc, void* hip_stream);
 int sphere_poisson_solve(sp_plan plan, const double* f, double* u, double integral,
                          void* hip_stream, sp_info* info);
 
+/* The same solve for a right-hand side given in low-rank form (Section 3,
+ * eq. lowrankRepresentation):
+ *   f(lambda_i, theta_j) = sum_{q < rank} d[q] c[q*m + j] r[q*n + i],
+ * c ([rank][m], samples of c_q at theta_j), r ([rank][n], samples of r_q at
+ * lambda_i) and d ([rank]) all device float64.  The half spectrum of sin^2 f
+ * in lambda is formed from the rank real DFTs of the rows of r and a rank-K
+ * product (Section 4, Computation of Fourier coefficients: the coefficients
+ * of a low-rank function come from 1D transforms of its factors), replacing
+ * the transform of the m x n grid; the theta pass and the inverse transform
+ * are those of sphere_poisson_solve, so u equals that call's result on the
+ * sampled grid up to rounding.  u: output [m][n] as there (MIXED: scratch
+ * until the end of the solve).  The call also uses the plan's second spectrum
+ * buffer for the factor spectra (calls on one plan are stream-ordered).
+ * Errors: SP_ERR_BAD_PLAN; SP_ERR_INVALID_ARG (a NULL pointer, rank < 1 or
+ * rank > m); SP_ERR_ALIAS (u overlaps c, r or d); SP_ERR_HIP;
+ * SP_ERR_NOT_CONVERGED as for sphere_poisson_solve. */
+int sphere_poisson_solve_lowrank(sp_plan plan, int rank, const double* d, const double* c, const double* r,
+                                 double* u, double integral, void* hip_stream, sp_info* info);
+
 /* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
  * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
  * for any loss; same layout, ownership and errors as sphere_poisson_solve. */
@@ -224,7 +243,8 @@ typedef enum {
     SP_KERNEL_LAMBDA_UPD = 5,   /* MIXED: float32 inverse lambda DFT of the correction + float64 update of u */
     SP_KERNEL_REDUCE = 6,       /* norms for the convergence report */
     SP_KERNEL_LAMBDA_GRAD = 7,  /* tangential gradient: both inverse lambda DFTs of a row, combined */
-    SP_KERNEL_KINDS = 8
+    SP_KERNEL_LOWRANK = 8,      /* low-rank right-hand side: rank-K product into the half spectrum */
+    SP_KERNEL_KINDS = 9
 } sp_kernel_kind;
 
 /* Diagnostic profiling: with `capacity` > 0 every later kernel launch of this

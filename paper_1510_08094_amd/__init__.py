@@ -74,6 +74,7 @@ def library():
     lib.sphere_poisson_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SpDesc), vp]
     lib.sphere_poisson_solve.argtypes = [vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_solve_adjoint.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_solve_lowrank.argtypes = [vp, ci, vp, vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_solve_batch.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                                ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp,
                                                ctypes.POINTER(SpInfo)]
@@ -95,7 +96,7 @@ def library():
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
-                 "sphere_poisson_vorticity", "sphere_poisson_integral"):
+                 "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -149,6 +150,26 @@ class SpherePoisson:
                                                   ctypes.c_void_p(u.data_ptr()), float(integral),
                                                   ctypes.c_void_p(_stream_handle(self.device)),
                                                   ctypes.byref(self.info)))
+        return u
+
+    def solve_lowrank(self, d: torch.Tensor, c: torch.Tensor, r: torch.Tensor, integral: float = 0.0,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+        """Solve for f = sum_q d[q] c[q](theta) r[q](lambda) given as factors:
+        d [K], c [K, m] (samples at theta_j), r [K, n] (samples at lambda_i),
+        float64 device tensors (Section 3, eq. lowrankRepresentation)."""
+        K = d.shape[0] if isinstance(d, torch.Tensor) and d.dim() == 1 else -1
+        if K < 1:
+            raise ValueError("d must be a 1-D tensor of length rank >= 1")
+        _check_grid(c, K, self.m, "c")
+        _check_grid(r, K, self.n, "r")
+        _check_grid(d.view(1, K), 1, K, "d")
+        u = torch.empty((self.m, self.n), dtype=torch.float64, device=c.device) if out is None else out
+        _check_grid(u, self.m, self.n, "out")
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_solve_lowrank(
+                self._plan, K, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(u.data_ptr()), float(integral),
+                ctypes.c_void_p(_stream_handle(self.device)), ctypes.byref(self.info)))
         return u
 
     def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -224,7 +245,7 @@ class SpherePoisson:
         return self._field_call("sphere_poisson_vorticity", [fx, fy, fz], 1, None if out is None else [out])
 
     KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce",
-                    "lambda_grad")
+                    "lambda_grad", "lowrank")
 
     def profile_enable(self, capacity: int):
         """Bracket the next `capacity` kernel launches with HIP events."""

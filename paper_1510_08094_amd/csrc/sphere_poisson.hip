@@ -23,6 +23,7 @@
 #include "sp_batch.hpp"
 #include "sp_theta_real.hpp"
 #include "sp_calculus.hpp"
+#include "sp_lowrank.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
@@ -1070,6 +1071,11 @@ bool overlap(const void* a, const void* b, size_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
+bool overlap(const void* a, const void* b, size_t abytes, size_t bbytes) {
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
 // One FP64 pass over the three kernels: lambda forward, theta, lambda inverse.
 int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool fwd_sin2,
              bool adjoint_weights, bool want_fint, hipStream_t s) {
@@ -1085,11 +1091,11 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     la.n = n; la.m = m; la.N = N; la.rw_log2 = p->rw_log2; la.lay_log2 = p->lay_log2;
     la.fft = p->fft_lam;
     la.nthr = p->lam_threads;
-    // forward lambda
+    // forward lambda (in == nullptr: spec64 already holds the right-hand side's spectrum)
     la.rowscale = fwd_sin2 ? p->sin2 : nullptr;
     if (!adjoint_weights) { la.w_mid = 1.0 / n; la.w_end = 1.0 / n; }
     else { la.w_mid = 2.0; la.w_end = 1.0; }
-    {
+    if (in) {
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
         hipLaunchKernelGGL(p->kd.fwd, dim3(p->lam_grid), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
     }
@@ -1168,7 +1174,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     la.nthr = p->lam_threads;
     la.w_mid = adjoint ? 2.0 : 1.0 / n;
     la.w_end = adjoint ? 1.0 : 1.0 / n;
-    {
+    if (f) {   // f == nullptr: spec64 already holds the right-hand side's spectrum
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
         hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
     }
@@ -1283,6 +1289,56 @@ extern "C" int sphere_poisson_solve(sp_plan p, const double* f, double* u, doubl
         return finish_info(p, s, info, SP_OK, p->desc.max_refine);
     }
     int st = run_fp64(p, f, u, sp::kSolve, integral / (4.0 * PI), true, false, true, s);
+    if (st != SP_OK) return st;
+    return finish_info(p, s, info, SP_OK, 0);
+}
+
+// Low-rank right-hand side: the lambda pass on the K rows of r (row scale d,
+// one row per workgroup, rows contiguous) into specB, then the rank-K product
+// into spec64; specB is free until the theta pass writes it.
+int lowrank_rhs(sp_plan p, int rank, const double* d, const double* c, const double* r, hipStream_t s) {
+    const int n = p->n, N = p->N;
+    sp::LambdaArgs<double> la{};
+    la.x = r; la.spec = p->specB; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n;
+    la.rowscale = d;
+    la.n = n; la.m = rank; la.N = N; la.rw_log2 = 0; la.lay_log2 = 0;
+    la.fft = p->fft_lam; la.nthr = p->lam_threads;
+    la.w_mid = 1.0 / n; la.w_end = 1.0 / n;
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(round_up(rank, 8)), dim3(round_up(p->lam_threads, 64)),
+                           p->lam_lds >> p->rw_log2, s, la);
+    }
+    {
+        ProfScope ps(p, SP_KERNEL_LOWRANK, s);
+        const dim3 grid(ceil_div(p->m, sp::kLowRankRows), ceil_div(N + 1, sp::kLowRankThreads));
+        hipLaunchKernelGGL(sp::k_lowrank_rhs<sp::kLowRankRows>, grid, dim3(sp::kLowRankThreads), 0, s,
+                           (const double*)c, (const double*)p->sin2, (const Cx<double>*)p->specB, p->spec64, rank,
+                           p->m, N, p->lay_log2);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
+}
+
+extern "C" int sphere_poisson_solve_lowrank(sp_plan p, int rank, const double* d, const double* c, const double* r,
+                                            double* u, double integral, void* hip_stream, sp_info* info) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!d || !c || !r || !u || rank < 1 || rank > p->m) return SP_ERR_INVALID_ARG;
+    const size_t ub = (size_t)p->n * p->m * sizeof(double);
+    if (overlap(u, c, ub, (size_t)rank * p->m * sizeof(double)) ||
+        overlap(u, r, ub, (size_t)rank * p->n * sizeof(double)) || overlap(u, d, ub, (size_t)rank * sizeof(double)))
+        return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int st = lowrank_rhs(p, rank, d, c, r, s);
+    if (st != SP_OK) return st;
+    const double PI = 3.14159265358979323846;
+    if (p->desc.precision == SP_MIXED) {
+        st = run_mixed(p, nullptr, u, integral / (4.0 * PI), false, s);
+        if (st != SP_OK) return st;
+        return finish_info(p, s, info, SP_OK, p->desc.max_refine);
+    }
+    st = run_fp64(p, nullptr, u, sp::kSolve, integral / (4.0 * PI), true, false, true, s);
     if (st != SP_OK) return st;
     return finish_info(p, s, info, SP_OK, 0);
 }
