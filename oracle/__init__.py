@@ -26,3 +26,4 @@ eigenvalue statement, closed-form solutions, brute-force dense solves).
 from .sphere_poisson import *  # noqa: F401,F403
 from .calculus import *  # noqa: F401,F403
 from .lowrank import *  # noqa: F401,F403
+from .evaluate import *  # noqa: F401,F403
