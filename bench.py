@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
     ap.add_argument("--no-gradient", action="store_true", help="skip the tangential-gradient measurement")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank right-hand side measurement")
+    ap.add_argument("--no-eval", action="store_true", help="skip the pointwise-evaluation measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 800 MB device-to-device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -239,6 +240,8 @@ def main():
         out["gradient"] = bench_gradient(args, P, torch, n, m)
     if not args.no_lowrank:
         out["lowrank"] = bench_lowrank(args, P, S, torch, np, n, m)
+    if not args.no_eval:
+        out["evaluation"] = bench_evaluate(args, P, S, torch, np)
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
@@ -356,6 +359,53 @@ def bench_lowrank(args, P, S, torch, np, n, m, L=12):
         res[prec] = {"ms_per_solve": ms, "dof_per_s": n * m / (ms * 1e-3), "kernels": kern,
                      "rel_err_vs_closed_form": err}
     return res
+
+
+def bench_evaluate(args, P, S, torch, np, n=150, m=150, L=12, npts=10 ** 6):
+    """Pointwise evaluation of a rank-25 field given by its factors on the
+    150 x 150 grid (the size of the paper's Poisson example) at 10^6 random
+    points of the sphere: time per call (coefficients + evaluation), library
+    HIP-event kernel times, and the evaluation kernel against the float64
+    vector FMA peak (it is bound by arithmetic, not memory)."""
+    K = 2 * L + 1
+    d, C, R = S.sphere_field_factors(22, 0, n, m, L)
+    rng = np.random.default_rng(23)
+    v = rng.standard_normal((npts, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    dg, Cg, Rg, pg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (d, C, R, v))
+    out = torch.empty(npts, dtype=torch.float64, device="cuda")
+    plan = P.SpherePoisson(n, m, "fp64")
+    for _ in range(max(1, args.warmup)):
+        plan.eval_lowrank(dg, Cg, Rg, pg, out=out)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    plan.profile_enable(4 * steps)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.eval_lowrank(dg, Cg, Rg, pg, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    prof = plan.profile_read()
+    plan.profile_enable(0)
+    plan.close()
+    # per point and factor: m Horner steps on two theta series (2 complex products + 2 adds,
+    # 14 flops) and n/4 + 1 steps on two lambda series (16 flops), plus the combination
+    N = n // 2
+    flops = npts * K * (14 * m + 16 * (N // 2 + 1) + 8)
+    ev = prof.get("eval", (float("nan"), 1))
+    ev_ms = ev[0] / ev[1]
+    peak = 78.6e12
+    kern = {k: {"avg_ms": round(t / c, 5), "launches": c} for k, (t, c) in prof.items()}
+    log("bench: evaluation %.3f ms/call (%d points, rank %d, %dx%d), eval kernel %.3f ms = %.1f TFLOP/s"
+        % (ms, npts, K, n, m, ev_ms, flops / (ev_ms * 1e-3) / 1e12))
+    return {"workload": "eval_lowrank_rank%d_n%d_m%d_points%d" % (K, n, m, npts), "ms_per_call": ms,
+            "points_per_s": npts / (ms * 1e-3), "kernels": kern,
+            "eval_roofline": {"bound": "alu", "achieved": flops / (ev_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                              "unit": "TFLOP/s", "frac": flops / (ev_ms * 1e-3) / peak,
+                              "flops_per_launch": flops}}
 
 
 def bench_batch(args, P, S, torch, np):

@@ -142,6 +142,27 @@ int sphere_poisson_solve(sp_plan plan, const double* f, double* u, double integr
 int sphere_poisson_solve_lowrank(sp_plan plan, int rank, const double* d, const double* c, const double* r,
                                  double* u, double integral, void* hip_stream, sp_info* info);
 
+/* Pointwise evaluation of a low-rank function (Section 4, Pointwise
+ * evaluation): out[p] = f(xyz[3p], xyz[3p+1], xyz[3p+2]) for f given as in
+ * sphere_poisson_solve_lowrank (d, c, r on the plan's grid).  A point is
+ * projected radially to the unit sphere: lambda = atan2(y, x),
+ * theta = arccos(z / |p|) (the origin gives NaN).  The factors are
+ * continued off the grid by their trigonometric interpolants with the DFS
+ * even/odd structure (eq. lowrankRepresentationSplit):
+ *   f = sum_q d_q (c_q^e(theta) r_q^+(lambda) + c_q^o(theta) r_q^-(lambda)),
+ * c^e = sum_{s<m} alpha_s cos(s theta) and c^o = sum_{s=1..m} beta_s sin(s theta)
+ * interpolating c_q at the m nodes, r^+ / r^- the even / odd wavenumbers of
+ * the real Fourier interpolant of r_q (Nyquist term as a cosine); each series
+ * is summed by Horner's rule, O(rank (m + n)) per point.  At the grid nodes
+ * the result is the sampled f.  xyz: device [npts][3]; out: device [npts].
+ * The coefficients are kept in the plan's spectrum buffers (stream-ordered
+ * with the plan's other calls); computing them costs O(rank m^2).
+ * Errors: SP_ERR_BAD_PLAN; SP_ERR_INVALID_ARG (a NULL pointer, npts < 0,
+ * rank < 1 or rank > min(m, n/2 + 1)); SP_ERR_ALIAS (out overlaps an input);
+ * SP_ERR_HIP.  npts = 0 does nothing. */
+int sphere_poisson_eval_lowrank(sp_plan plan, int rank, const double* d, const double* c, const double* r,
+                                int npts, const double* xyz, double* out, void* hip_stream);
+
 /* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
  * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
  * for any loss; same layout, ownership and errors as sphere_poisson_solve. */
@@ -244,7 +265,9 @@ typedef enum {
     SP_KERNEL_REDUCE = 6,       /* norms for the convergence report */
     SP_KERNEL_LAMBDA_GRAD = 7,  /* tangential gradient: both inverse lambda DFTs of a row, combined */
     SP_KERNEL_LOWRANK = 8,      /* low-rank right-hand side: rank-K product into the half spectrum */
-    SP_KERNEL_KINDS = 9
+    SP_KERNEL_EVAL_COEFFS = 9,  /* pointwise evaluation: cosine / sine coefficients of the theta factors */
+    SP_KERNEL_EVAL = 10,        /* pointwise evaluation: Horner sums at the points */
+    SP_KERNEL_KINDS = 11
 } sp_kernel_kind;
 
 /* Diagnostic profiling: with `capacity` > 0 every later kernel launch of this

@@ -75,6 +75,7 @@ def library():
     lib.sphere_poisson_solve.argtypes = [vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_solve_adjoint.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_solve_lowrank.argtypes = [vp, ci, vp, vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_eval_lowrank.argtypes = [vp, ci, vp, vp, vp, ci, vp, vp, vp]
     lib.sphere_poisson_solve_batch.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                                ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp,
                                                ctypes.POINTER(SpInfo)]
@@ -96,7 +97,8 @@ def library():
                  "sphere_poisson_solve_batch", "sphere_poisson_destroy",
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
-                 "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank"):
+                 "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank",
+                 "sphere_poisson_eval_lowrank"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -172,6 +174,30 @@ class SpherePoisson:
                 ctypes.c_void_p(_stream_handle(self.device)), ctypes.byref(self.info)))
         return u
 
+    def eval_lowrank(self, d: torch.Tensor, c: torch.Tensor, r: torch.Tensor, xyz: torch.Tensor,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """f at the points xyz [P, 3] (projected radially to the sphere) for f
+        given by the factors d [K], c [K, m], r [K, n] on the plan's grid
+        (Section 4, Pointwise evaluation)."""
+        K = d.shape[0] if isinstance(d, torch.Tensor) and d.dim() == 1 else -1
+        if K < 1:
+            raise ValueError("d must be a 1-D tensor of length rank >= 1")
+        _check_grid(c, K, self.m, "c")
+        _check_grid(r, K, self.n, "r")
+        _check_grid(d.view(1, K), 1, K, "d")
+        if xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape (P, 3)")
+        P = xyz.shape[0]
+        _check_grid(xyz, P, 3, "xyz")
+        o = torch.empty(P, dtype=torch.float64, device=xyz.device) if out is None else out
+        _check_grid(o.view(1, -1) if o.dim() == 1 else o, 1, P, "out")
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_eval_lowrank(
+                self._plan, K, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                ctypes.c_void_p(r.data_ptr()), P, ctypes.c_void_p(xyz.data_ptr()), ctypes.c_void_p(o.data_ptr()),
+                ctypes.c_void_p(_stream_handle(self.device))))
+        return o
+
     def adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         _check_grid(g, self.m, self.n, "g")
         fb = torch.empty_like(g) if out is None else out
@@ -245,7 +271,7 @@ class SpherePoisson:
         return self._field_call("sphere_poisson_vorticity", [fx, fy, fz], 1, None if out is None else [out])
 
     KERNEL_KINDS = ("lambda_fwd", "theta", "lambda_inv", "lambda_mix", "theta_resid", "lambda_upd", "reduce",
-                    "lambda_grad", "lowrank")
+                    "lambda_grad", "lowrank", "eval_coeffs", "eval")
 
     def profile_enable(self, capacity: int):
         """Bracket the next `capacity` kernel launches with HIP events."""

@@ -99,4 +99,108 @@ __global__ void __launch_bounds__(kLowRankThreads)
     }
 }
 
+// ------------------------------------------------------------ evaluation
+// Pointwise evaluation of a low-rank function (Section 4, Pointwise
+// evaluation): at a point p, projected radially to the sphere,
+//   f(p) = sum_q d_q (c_q^e(theta) r_q^+(lambda) + c_q^o(theta) r_q^-(lambda)),
+// the factors' trigonometric interpolants with the even/odd structure of the
+// DFS split (eq. lowrankRepresentationSplit): c^e the cosine interpolant of the
+// theta samples, c^o the sine interpolant, r^+- the even / odd wavenumbers of
+// the real Fourier interpolant of the lambda samples.  Each series is summed
+// by Horner's rule in e^{i theta} or e^{2 i (lambda + pi)}: O(K (m + n)) per
+// point, bound by the float64 FMA rate.
+
+// alpha[q][.] and beta[q][.] of factor q (one thread per coefficient index s):
+//   alpha_s = (2/m) sum_t c_q(theta_t) cos(s theta_t)      (halved for s = 0),
+//   beta_s  = (2/m) sum_t c_q(theta_t) sin((s+1) theta_t)  (halved for s = m-1),
+// the inverses of the cosine and sine sums on the half-shifted nodes
+// theta_t = (t + 1/2) pi / m; angles reduced exactly as s (2t + 1) mod 4m.
+__global__ void __launch_bounds__(256) k_trig_coeffs(const double* __restrict__ c, int m,
+                                                     double* __restrict__ alpha, double* __restrict__ beta) {
+    const int q = blockIdx.x;
+    const int s = blockIdx.y * 256 + threadIdx.x;
+    if (s >= m) return;
+    const double* cq = c + (size_t)q * m;
+    const long long m4 = 4LL * m;
+    const double inv2m = 1.0 / (2.0 * m);
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < m; ++t) {
+        const double v = cq[t];
+        const long long odd = 2LL * t + 1;
+        const double ac = (double)(((long long)s * odd) % m4) * inv2m;
+        const double as = (double)(((long long)(s + 1) * odd) % m4) * inv2m;
+        a = fma(v, cospi(ac), a);
+        b = fma(v, sinpi(as), b);
+    }
+    const double w = 2.0 / m;
+    alpha[(size_t)q * m + s] = a * (s == 0 ? 0.5 * w : w);
+    beta[(size_t)q * m + s] = b * (s == m - 1 ? 0.5 * w : w);
+}
+
+// One thread per point.  h: the lambda coefficients of the factors, already
+// multiplied by d_q and by the real-series weights (1 at k = 0 and k = n/2,
+// 2 between), contiguous rows of N + 1 values.
+__global__ void __launch_bounds__(256) k_eval_lowrank(const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta,
+                                                      const Cx<double>* __restrict__ h, int K, int m, int N,
+                                                      const double* __restrict__ xyz, int npts,
+                                                      double* __restrict__ out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npts) return;
+    const double x = xyz[3 * (size_t)p], y = xyz[3 * (size_t)p + 1], z = xyz[3 * (size_t)p + 2];
+    const double rho = sqrt(x * x + y * y + z * z);
+    // e^{i theta} = (z, sqrt(x^2 + y^2)) / rho; e^{i (lambda + pi)} = -e^{i lambda}, lambda = atan2(y, x)
+    const Cx<double> zt{fmin(fmax(z / rho, -1.0), 1.0), sqrt(x * x + y * y) / rho};
+    double sl, cl;
+    sincos(atan2(y, x), &sl, &cl);
+    const Cx<double> v{-cl, -sl};
+    const Cx<double> u = cmul(v, v);
+    double acc = 0.0;
+    for (int q = 0; q < K; ++q) {
+        const double* aq = alpha + (size_t)q * m;
+        const double* bq = beta + (size_t)q * m;
+        Cx<double> pe{0.0, 0.0}, po{0.0, 0.0};
+        int s = m - 1;
+        for (; s >= 3; s -= 4) {   // four coefficients per scalar-load batch
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pe = cmul(pe, zt);
+                po = cmul(po, zt);
+                pe.x += aq[s - e];
+                po.x += bq[s - e];
+            }
+        }
+        for (; s >= 0; --s) {
+            pe = cmul(pe, zt);
+            po = cmul(po, zt);
+            pe.x += aq[s];
+            po.x += bq[s];
+        }
+        const double ce = pe.x;                    // sum alpha_s cos(s theta)
+        const double co = cmul(po, zt).y;          // sum beta_s sin((s + 1) theta)
+        const Cx<double>* hq = h + (size_t)q * (N + 1);
+        // even terms h_{2j} and odd terms h_{2j+1} as polynomials in u; for even N
+        // the top even term h_N has no odd partner and starts the even sum
+        Cx<double> pp{0.0, 0.0}, pm{0.0, 0.0};
+        int k2 = N / 2;
+        if (!(N & 1)) {
+            pp = hq[N];
+            --k2;
+        }
+        for (; k2 >= 0; --k2) {
+            pp = cmul(pp, u);
+            pm = cmul(pm, u);
+            const Cx<double> he = hq[2 * k2], ho = hq[2 * k2 + 1];
+            pp.x += he.x;
+            pp.y += he.y;
+            pm.x += ho.x;
+            pm.y += ho.y;
+        }
+        const double rp = pp.x;                    // even wavenumbers
+        const double rm = cmul(pm, v).x;           // odd wavenumbers
+        acc += ce * rp + co * rm;
+    }
+    out[p] = acc;
+}
+
 }  // namespace sp

@@ -1343,6 +1343,47 @@ extern "C" int sphere_poisson_solve_lowrank(sp_plan p, int rank, const double* d
     return finish_info(p, s, info, SP_OK, 0);
 }
 
+extern "C" int sphere_poisson_eval_lowrank(sp_plan p, int rank, const double* d, const double* c, const double* r,
+                                           int npts, const double* xyz, double* out, void* hip_stream) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!d || !c || !r || rank < 1 || rank > p->m || rank > p->N + 1 || npts < 0) return SP_ERR_INVALID_ARG;
+    if (npts == 0) return SP_OK;
+    if (!xyz || !out) return SP_ERR_INVALID_ARG;
+    const size_t ob = (size_t)npts * sizeof(double);
+    if (overlap(out, xyz, ob, 3 * ob) || overlap(out, c, ob, (size_t)rank * p->m * sizeof(double)) ||
+        overlap(out, r, ob, (size_t)rank * p->n * sizeof(double)) || overlap(out, d, ob, (size_t)rank * sizeof(double)))
+        return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = p->n, m = p->m, N = p->N;
+    // lambda coefficients of the rows of r, times d and the real-series weights -> specB
+    sp::LambdaArgs<double> la{};
+    la.x = r; la.spec = p->specB; la.tw = p->t64.tw_n; la.ptw = p->t64.pass_n;
+    la.rowscale = d;
+    la.n = n; la.m = rank; la.N = N; la.rw_log2 = 0; la.lay_log2 = 0;
+    la.fft = p->fft_lam; la.nthr = p->lam_threads;
+    la.w_mid = 2.0 / n; la.w_end = 1.0 / n;
+    {
+        ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
+        hipLaunchKernelGGL(p->kd.fwd, dim3(round_up(rank, 8)), dim3(round_up(p->lam_threads, 64)),
+                           p->lam_lds >> p->rw_log2, s, la);
+    }
+    // cosine and sine coefficients of the theta factors -> spec64 (2 rank m <= 2 m (N + 1) doubles)
+    double* alpha = reinterpret_cast<double*>(p->spec64);
+    double* beta = alpha + (size_t)rank * m;
+    {
+        ProfScope ps(p, SP_KERNEL_EVAL_COEFFS, s);
+        hipLaunchKernelGGL(sp::k_trig_coeffs, dim3(rank, ceil_div(m, 256)), dim3(256), 0, s, c, m, alpha, beta);
+    }
+    {
+        ProfScope ps(p, SP_KERNEL_EVAL, s);
+        hipLaunchKernelGGL(sp::k_eval_lowrank, dim3(ceil_div(npts, 256)), dim3(256), 0, s, (const double*)alpha,
+                           (const double*)beta, (const Cx<double>*)p->specB, rank, m, N, xyz, npts, out);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return SP_OK;
+}
+
 extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* fbar, void* hip_stream,
                                             sp_info* info) {
     if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
