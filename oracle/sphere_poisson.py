@@ -6,7 +6,7 @@ Notation follows the paper: lambda is the azimuth, theta the colatitude,
 [m, n]: row j is theta_j = (j + 1/2) pi / m, column i is
 lambda_i = -pi + 2 pi i / n, with n even.
 
-Readings of the paper taken here (each is also listed in the design doc):
+Readings of the paper taken here:
 
 * The per-wavenumber systems of eq. (linearSystems) are taken with the sign
   that column k of the Sylvester equation (SylvesterSphericalPoisson) implies,
