@@ -27,3 +27,4 @@ from .sphere_poisson import *  # noqa: F401,F403
 from .calculus import *  # noqa: F401,F403
 from .lowrank import *  # noqa: F401,F403
 from .evaluate import *  # noqa: F401,F403
+from .ge import *  # noqa: F401,F403
