@@ -67,13 +67,14 @@ def log(*a):
 
 
 def source_digest() -> str:
-    """sha256 of the HIP sources: a measured traffic record applies only to the
-    kernels it was taken on."""
+    """sha256 of the solver's HIP sources: a measured traffic record applies only
+    to the kernels it was taken on.  The Gaussian-elimination constructor
+    (sp_ge*) is a translation unit of its own and takes no part in them."""
     import hashlib
     d = os.path.join(ROOT, "paper_1510_08094_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".h")):
+        if name.endswith((".hip", ".hpp", ".h")) and not name.startswith("sp_ge"):
             with open(os.path.join(d, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -114,6 +115,7 @@ def main():
     ap.add_argument("--no-gradient", action="store_true", help="skip the tangential-gradient measurement")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank right-hand side measurement")
     ap.add_argument("--no-eval", action="store_true", help="skip the pointwise-evaluation measurement")
+    ap.add_argument("--no-ge", action="store_true", help="skip the Gaussian-elimination constructor measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 800 MB device-to-device copy (the reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -241,6 +243,8 @@ def main():
         out["lowrank"] = bench_lowrank(args, P, S, torch, np, n, m)
     if not args.no_eval:
         out["evaluation"] = bench_evaluate(args, P, S, torch, np)
+    if not args.no_ge:
+        out["ge"] = bench_ge(args, P, S, torch, np, n, m)
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
@@ -405,6 +409,39 @@ def bench_evaluate(args, P, S, torch, np, n=150, m=150, L=12, npts=10 ** 6):
             "eval_roofline": {"bound": "alu", "achieved": flops / (ev_ms * 1e-3) / 1e12, "peak": peak / 1e12,
                               "unit": "TFLOP/s", "frac": flops / (ev_ms * 1e-3) / peak,
                               "flops_per_launch": flops}}
+
+
+def bench_ge(args, P, S, torch, np, n, m, L=12):
+    """Low-rank approximation by structure-preserving Gaussian elimination of a
+    band-limited field of degree 12 (rank 25) sampled on the workload grid:
+    time per call with the samples resident, steps until the tolerance stops
+    the loop, reconstruction error on every 97th row, and the HBM rate of the
+    whole call against its algorithmic bytes (per step: one read of the grid
+    for the pivot search, one read and one write for the update)."""
+    f = torch.from_numpy(S.sphere_field(24, 0, n, m, L)).cuda()
+    steps = 2 * L + 2
+    for _ in range(max(1, args.warmup)):
+        d, c, r, piv = P.ge_lowrank(f, steps, 0.01, 1e-12)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        d, c, r, piv = P.ge_lowrank(f, steps, 0.01, 1e-12)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    active = int((piv[:, 0] >= 0).sum())
+    rows = torch.arange(0, m, 97, device=f.device)
+    rec = (c[:, rows].T * d[None, :]) @ r
+    err = float((rec - f[rows]).abs().max() / f.abs().max())
+    # active steps: search (8 B per sample) + update (16 B); the step that stops the loop only searches
+    alg = n * m * (24 * active + (8 if active < steps else 0))
+    log("bench: ge %.3f ms/call (%d steps, %d active), rel err %.2e, %.0f GB/s" % (ms, steps, active, err,
+                                                                                    alg / (ms * 1e-3) / 1e9))
+    return {"workload": "ge_lowrank_rank%d_n%d_m%d" % (2 * L + 1, n, m), "ms_per_call": ms, "steps": steps,
+            "active_steps": active, "rel_err_rows": err, "alg_bytes": alg, "alg_GBps": alg / (ms * 1e-3) / 1e9}
 
 
 def bench_batch(args, P, S, torch, np):

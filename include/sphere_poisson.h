@@ -163,6 +163,40 @@ int sphere_poisson_solve_lowrank(sp_plan plan, int rank, const double* d, const 
 int sphere_poisson_eval_lowrank(sp_plan plan, int rank, const double* d, const double* c, const double* r,
                                 int npts, const double* xyz, double* out, void* hip_stream);
 
+/* Low-rank approximation of a sampled function by structure-preserving
+ * Gaussian elimination (Section 3, Figure GaussianElimination, eq.
+ * GEstructurePreservingStepPseudoinverse), on the grid f [m][n] (device,
+ * float64, theta_j rows, lambda_i columns, n even).  The doubled function is
+ * never formed: its value at (lambda, -theta) is the sample at
+ * (lambda + pi, theta).  Step k:
+ *   pivot: the grid point (theta_t, lambda_i), lambda_i in [0, pi), whose 2 x 2
+ *     pivot matrix M = [[a, b], [b, a]], a = e(lambda_i - pi, theta_t),
+ *     b = e(lambda_i, theta_t), has the largest sigma_1 = |a| + |b|
+ *     (eq. SingularValues; ties go to the first point in row-major order);
+ *   eps = alpha sigma_1; M's eps-pseudoinverse keeps 1/(a+b), 1/(a-b) where
+ *     |a +- b| > eps (Definition pseudoinverse);
+ *   the residual e loses the resulting rank-2 term, written as two rank-1
+ *     terms d (C0 +- C1)(R0 +- R1) with d = 1/(2 (a +- b)) or 0, C0 / C1 the
+ *     residual's columns at lambda - pi / lambda, R0 its row at theta and R1
+ *     that row shifted by pi (eq. lowrankRepresentationSplit).
+ * Outputs (device): d [2 steps], c [2 steps][m], r [2 steps][n] in the form
+ * sphere_poisson_solve_lowrank and sphere_poisson_eval_lowrank take (f is
+ * approximated by sum_q d[q] c[q] r[q]); pivots [steps][2] (t, i), or NULL.
+ * The loop stops once sigma_1 <= tol times the first step's sigma_1; the
+ * remaining steps write d = 0, zero factors and pivots -1.  The pole
+ * zero-out step of eq. ZeroOut is not applied (the grid has no pole samples).
+ * work: device workspace of sphere_poisson_ge_workspace_bytes(n, m) bytes
+ * (the residual and the pivot search's partials), 16-byte aligned, as is r.
+ * Each step is three launches on hip_stream: pivot search (one read of the
+ * grid), pivot and factor extraction, rank-2 update (one read and write).
+ * Errors: SP_ERR_INVALID_ARG (sizes, steps < 1, alpha outside [0, 1],
+ * tol < 0, a NULL pointer, a small or misaligned workspace); SP_ERR_ALIAS
+ * (outputs overlapping f, the workspace or each other); SP_ERR_HIP. */
+size_t sphere_poisson_ge_workspace_bytes(int n_lambda, int m_theta);
+int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int steps, double alpha, double tol,
+                              void* work, size_t work_bytes, double* d, double* c, double* r, int* pivots,
+                              void* hip_stream);
+
 /* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
  * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
  * for any loss; same layout, ownership and errors as sphere_poisson_solve. */

@@ -76,6 +76,9 @@ def library():
     lib.sphere_poisson_solve_adjoint.argtypes = [vp, vp, vp, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_solve_lowrank.argtypes = [vp, ci, vp, vp, vp, vp, cd, vp, ctypes.POINTER(SpInfo)]
     lib.sphere_poisson_eval_lowrank.argtypes = [vp, ci, vp, vp, vp, ci, vp, vp, vp]
+    lib.sphere_poisson_ge_workspace_bytes.argtypes = [ci, ci]
+    lib.sphere_poisson_ge_workspace_bytes.restype = ctypes.c_size_t
+    lib.sphere_poisson_ge_lowrank.argtypes = [ci, ci, vp, ci, cd, cd, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
     lib.sphere_poisson_solve_batch.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                                ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp,
                                                ctypes.POINTER(SpInfo)]
@@ -98,7 +101,7 @@ def library():
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
                  "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank",
-                 "sphere_poisson_eval_lowrank"):
+                 "sphere_poisson_eval_lowrank", "sphere_poisson_ge_lowrank"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -308,6 +311,34 @@ class SpherePoissonFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g: torch.Tensor):
         return ctx.plan.adjoint(g.contiguous()), None
+
+
+def ge_lowrank(f: torch.Tensor, steps: int, alpha: float = 0.01, tol: float = 0.0):
+    """Low-rank approximation of the sampled f [m, n] (float64, device) by
+    structure-preserving Gaussian elimination (Section 3, Figure
+    GaussianElimination): returns (d [2 steps], c [2 steps, m], r [2 steps, n],
+    pivots [steps, 2]) with f ~ sum_q d[q] c[q](theta) r[q](lambda), the form
+    SpherePoisson.solve_lowrank and eval_lowrank take."""
+    if not isinstance(f, torch.Tensor) or f.dim() != 2:
+        raise ValueError("f must be a 2-D tensor (m, n)")
+    m, n = f.shape
+    _check_grid(f, m, n, "f")
+    lib = library()
+    wb = int(lib.sphere_poisson_ge_workspace_bytes(n, m))
+    if wb == 0:
+        raise SpError(1, "unsupported grid for the Gaussian elimination")
+    dev = f.device
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    d = torch.empty(2 * steps, dtype=torch.float64, device=dev)
+    c = torch.empty((2 * steps, m), dtype=torch.float64, device=dev)
+    r = torch.empty((2 * steps, n), dtype=torch.float64, device=dev)
+    piv = torch.empty((steps, 2), dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.sphere_poisson_ge_lowrank(n, m, ctypes.c_void_p(f.data_ptr()), int(steps), float(alpha), float(tol),
+                                             ctypes.c_void_p(work.data_ptr()), wb, ctypes.c_void_p(d.data_ptr()),
+                                             ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                             ctypes.c_void_p(piv.data_ptr()), ctypes.c_void_p(_stream_handle(dev))))
+    return d, c, r, piv
 
 
 def solve_batch(fs, precision: str = "mixed", outs=None):

@@ -9,7 +9,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "sphere_poisson.hip")
+# the solver, and the Gaussian-elimination constructor in a translation unit of its own
+SRCS = [os.path.join(HERE, "csrc", "sphere_poisson.hip"), os.path.join(HERE, "csrc", "sp_ge.hip")]
 OUT = os.path.join(HERE, "libsphere_poisson.so")
 ARCH = "gfx950"
 
@@ -30,13 +31,13 @@ def flags() -> list[str]:
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + ["-o", tmp, SRC]
+    cmd = [hipcc()] + flags() + ["-o", tmp] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for %s" % SRC)
+        raise RuntimeError("hipcc failed for %s" % " ".join(SRCS))
     os.replace(tmp, OUT)
     return OUT
 

@@ -1,0 +1,248 @@
+// Structure-preserving Gaussian elimination on the sampled grid (Section 3,
+// Figure GaussianElimination, eq. GEstructurePreservingStepPseudoinverse):
+// each step picks the 2 x 2 BMC pivot with the largest sigma_1 = |a| + |b|
+// (a = e(lambda* - pi, theta*), b = e(lambda*, theta*); eq. SingularValues),
+// inverts it through its eps-pseudoinverse (eps = alpha sigma_1), and removes
+// the resulting rank-2 term from the residual.  The doubled function is never
+// formed: its value at (lambda, -theta) is the sample at (lambda + pi, theta).
+// The two rank-1 terms of a step are d (C0 +- C1)(R0 +- R1) with d = 1 / (2 (a +- b))
+// (0 where |a +- b| <= eps), C0 / C1 the residual's columns at lambda* - pi /
+// lambda*, R0 the row at theta* and R1 that row shifted by pi.
+// A step is three launches: partial pivot search, pivot + factor extraction
+// (one workgroup), and the rank-2 update of the residual (HBM-bound: one read
+// of the grid for the search, one read and write for the update); once the
+// loop has stopped, the remaining launches return at once.
+// This translation unit is separate from the solver's: it owns no plan and
+// works in a workspace the caller provides.
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/sphere_poisson.h"
+
+namespace spge {
+
+constexpr int kGeBlocks = 1024;   // workgroups of the partial pivot search
+constexpr int kGeThreads = 256;
+
+struct GeRecord {      // device state carried from step to step
+    double s_first;    // sigma_1 of the first pivot
+    int active;        // 0 once the loop has stopped
+};
+
+// candidate (score, flat index t * (n/2) + i - n/2): larger score wins, ties go
+// to the smaller index (the first maximum in row-major order)
+__device__ __forceinline__ void ge_better(double s, long long idx, double& best, long long& bidx) {
+    if (s > best || (s == best && idx < bidx)) {
+        best = s;
+        bidx = idx;
+    }
+}
+
+__device__ __forceinline__ void ge_block_argmax(double& best, long long& bidx) {
+    __shared__ double sb[kGeThreads];
+    __shared__ long long si[kGeThreads];
+    sb[threadIdx.x] = best;
+    si[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int w = kGeThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double b = sb[threadIdx.x];
+            long long i = si[threadIdx.x];
+            ge_better(sb[threadIdx.x + w], si[threadIdx.x + w], b, i);
+            sb[threadIdx.x] = b;
+            si[threadIdx.x] = i;
+        }
+        __syncthreads();
+    }
+    best = sb[0];
+    bidx = si[0];
+}
+
+// 1. workgroup g scans rows g, g + G, ...: partial (score, index) per workgroup
+// (after the loop has stopped, every workgroup returns at once: no candidate)
+__global__ void __launch_bounds__(kGeThreads) k_ge_scores(const double* __restrict__ e, int m, int n,
+                                                         const GeRecord* __restrict__ rec, int k,
+                                                         double* __restrict__ pscore, long long* __restrict__ pidx) {
+    const int H = n / 2;
+    double best = -1.0;
+    long long bidx = 0x7fffffffffffffffLL;
+    if (k > 0 && rec->active == 0) {
+        if (threadIdx.x == 0) {
+            pscore[blockIdx.x] = best;
+            pidx[blockIdx.x] = bidx;
+        }
+        return;
+    }
+    for (int t = blockIdx.x; t < m; t += gridDim.x) {
+        const double* row = e + (size_t)t * n;
+        for (int ih = threadIdx.x; ih < H; ih += blockDim.x)
+            ge_better(fabs(row[ih]) + fabs(row[ih + H]), (long long)t * H + ih, best, bidx);
+    }
+    ge_block_argmax(best, bidx);
+    if (threadIdx.x == 0) {
+        pscore[blockIdx.x] = best;
+        pidx[blockIdx.x] = bidx;
+    }
+}
+
+// 2. one workgroup: the pivot, its pseudoinverse, and the factors of step k
+__global__ void __launch_bounds__(kGeThreads) k_ge_pivot(const double* __restrict__ e, int m, int n,
+                                                        const double* __restrict__ pscore,
+                                                        const long long* __restrict__ pidx, int nparts, int k,
+                                                        double alpha, double tol, GeRecord* __restrict__ rec,
+                                                        double* __restrict__ d, double* __restrict__ c,
+                                                        double* __restrict__ r, int* __restrict__ piv) {
+    const int H = n / 2;
+    double best = -1.0;
+    long long bidx = 0x7fffffffffffffffLL;
+    for (int g = threadIdx.x; g < nparts; g += blockDim.x) ge_better(pscore[g], pidx[g], best, bidx);
+    ge_block_argmax(best, bidx);
+    __shared__ double sh[2];
+    __shared__ int st[3];
+    if (threadIdx.x == 0) {
+        // no candidate at all (a residual of NaNs): stop, reading a valid point
+        const bool found = bidx != 0x7fffffffffffffffLL;
+        const int t = found ? (int)(bidx / H) : 0, i = found ? (int)(bidx % H) + H : H;
+        const double a = e[(size_t)t * n + i - H], b = e[(size_t)t * n + i];
+        const double s1 = found ? fabs(a) + fabs(b) : 0.0;
+        if (k == 0) {
+            rec->s_first = s1;
+            rec->active = 1;
+        }
+        int act = rec->active && s1 > 0.0 && !(s1 <= tol * rec->s_first);
+        rec->active = act;
+        const double eps = alpha * s1;
+        sh[0] = act && fabs(a + b) > eps ? 1.0 / (a + b) : 0.0;
+        sh[1] = act && fabs(a - b) > eps ? 1.0 / (a - b) : 0.0;
+        st[0] = t;
+        st[1] = i;
+        st[2] = act;
+        if (piv) {
+            piv[2 * k] = act ? t : -1;
+            piv[2 * k + 1] = act ? i : -1;
+        }
+        d[2 * k] = 0.5 * sh[0];
+        d[2 * k + 1] = 0.5 * sh[1];
+    }
+    __syncthreads();
+    const int t = st[0], i = st[1], act = st[2];
+    double* cp = c + (size_t)(2 * k) * m;
+    double* cm = cp + m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const double c0 = act ? e[(size_t)j * n + i - H] : 0.0, c1 = act ? e[(size_t)j * n + i] : 0.0;
+        cp[j] = c0 + c1;
+        cm[j] = c0 - c1;
+    }
+    double* rp = r + (size_t)(2 * k) * n;
+    double* rm = rp + n;
+    const double* row = e + (size_t)t * n;
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        const int ls = l + H < n ? l + H : l - H;
+        const double r0 = act ? row[l] : 0.0, r1 = act ? row[ls] : 0.0;
+        rp[l] = r0 + r1;
+        rm[l] = r0 - r1;
+    }
+}
+
+// 3. e -= d+ c+ r+^T + d- c- r-^T over the grid (two samples per thread step)
+__global__ void __launch_bounds__(kGeThreads) k_ge_update(double* __restrict__ e, int m, int n,
+                                                         const double* __restrict__ d, const double* __restrict__ c,
+                                                         const double* __restrict__ r, int k) {
+    const double dp = d[2 * k], dm = d[2 * k + 1];
+    if (dp == 0.0 && dm == 0.0) return;   // uniform: every workgroup takes the same branch
+    const double* cp = c + (size_t)(2 * k) * m;
+    const double* cm = cp + m;
+    const double2* rp = reinterpret_cast<const double2*>(r + (size_t)(2 * k) * n);
+    const double2* rm = reinterpret_cast<const double2*>(r + (size_t)(2 * k + 1) * n);
+    const int H = n / 2;
+    const size_t total = (size_t)m * H;
+    double2* e2 = reinterpret_cast<double2*>(e);
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int t = (int)(q / H), l = (int)(q - (size_t)t * H);
+        const double ap = dp * cp[t], am = dm * cm[t];
+        const double2 p = rp[l], mi = rm[l];
+        double2 v = e2[q];
+        v.x -= ap * p.x + am * mi.x;
+        v.y -= ap * p.y + am * mi.y;
+        e2[q] = v;
+    }
+}
+
+}  // namespace spge
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+struct GeLayout {
+    size_t off_e, off_score, off_idx, off_rec, total;
+};
+
+GeLayout ge_layout(int n, int m) {
+    GeLayout L{};
+    L.off_e = 0;
+    L.off_score = up((size_t)n * m * sizeof(double));
+    L.off_idx = L.off_score + up(spge::kGeBlocks * sizeof(double));
+    L.off_rec = L.off_idx + up(spge::kGeBlocks * sizeof(long long));
+    L.total = L.off_rec + up(sizeof(spge::GeRecord));
+    return L;
+}
+
+bool ge_sizes_ok(int n, int m) { return n >= 4 && !(n & 1) && m >= 1 && n <= (1 << 20) && m <= (1 << 20); }
+
+bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return !(x < y + nb && y < x + na);
+}
+
+}  // namespace
+
+extern "C" size_t sphere_poisson_ge_workspace_bytes(int n_lambda, int m_theta) {
+    if (!ge_sizes_ok(n_lambda, m_theta)) return 0;
+    return ge_layout(n_lambda, m_theta).total;
+}
+
+extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int steps, double alpha,
+                                         double tol, void* work, size_t work_bytes, double* d, double* c, double* r,
+                                         int* pivots, void* hip_stream) {
+    const int n = n_lambda, m = m_theta;
+    if (!ge_sizes_ok(n, m) || steps < 1 || !(alpha >= 0.0 && alpha <= 1.0) || !(tol >= 0.0)) return SP_ERR_INVALID_ARG;
+    if (!f || !work || !d || !c || !r) return SP_ERR_INVALID_ARG;
+    const GeLayout L = ge_layout(n, m);
+    if (work_bytes < L.total) return SP_ERR_INVALID_ARG;
+    if (((uintptr_t)work | (uintptr_t)r) & 15) return SP_ERR_INVALID_ARG;   // double2 access to the grid and rows
+    const size_t fb = (size_t)n * m * sizeof(double);
+    const size_t db = 2 * (size_t)steps * sizeof(double), cb = db * m, rb = db * n, pb = 2 * (size_t)steps * sizeof(int);
+    const void* outs[4] = {d, c, r, pivots};
+    const size_t ob[4] = {db, cb, rb, pivots ? pb : 0};
+    for (int a = 0; a < 4; ++a) {
+        if (!outs[a]) continue;
+        if (!disjoint(outs[a], ob[a], f, fb) || !disjoint(outs[a], ob[a], work, L.total)) return SP_ERR_ALIAS;
+        for (int b = a + 1; b < 4; ++b)
+            if (outs[b] && !disjoint(outs[a], ob[a], outs[b], ob[b])) return SP_ERR_ALIAS;
+    }
+    if (!disjoint(f, fb, work, L.total)) return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned char* w = static_cast<unsigned char*>(work);
+    double* e = reinterpret_cast<double*>(w + L.off_e);
+    double* ps = reinterpret_cast<double*>(w + L.off_score);
+    long long* pi = reinterpret_cast<long long*>(w + L.off_idx);
+    spge::GeRecord* rec = reinterpret_cast<spge::GeRecord*>(w + L.off_rec);
+    if (hipMemcpyAsync(e, f, fb, hipMemcpyDeviceToDevice, s) != hipSuccess) return SP_ERR_HIP;
+    const size_t pairs = (size_t)m * (n / 2);
+    const int ublocks = (int)((pairs + spge::kGeThreads - 1) / spge::kGeThreads < 4096
+                                  ? (pairs + spge::kGeThreads - 1) / spge::kGeThreads : 4096);
+    for (int k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(spge::k_ge_scores, dim3(spge::kGeBlocks), dim3(spge::kGeThreads), 0, s, (const double*)e, m,
+                           n, (const spge::GeRecord*)rec, k, ps, pi);
+        hipLaunchKernelGGL(spge::k_ge_pivot, dim3(1), dim3(spge::kGeThreads), 0, s, (const double*)e, m, n,
+                           (const double*)ps, (const long long*)pi, spge::kGeBlocks, k, alpha, tol, rec, d, c, r, pivots);
+        hipLaunchKernelGGL(spge::k_ge_update, dim3(ublocks), dim3(spge::kGeThreads), 0, s, e, m, n, (const double*)d,
+                           (const double*)c, (const double*)r, k);
+    }
+    if (hipGetLastError() != hipSuccess) return SP_ERR_HIP;
+    return SP_OK;
+}
