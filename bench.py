@@ -416,8 +416,9 @@ def bench_ge(args, P, S, torch, np, n, m, L=12):
     band-limited field of degree 12 (rank 25) sampled on the workload grid:
     time per call with the samples resident, steps until the tolerance stops
     the loop, reconstruction error on every 97th row, and the HBM rate of the
-    whole call against its algorithmic bytes (per step: one read of the grid
-    for the pivot search, one read and one write for the update)."""
+    whole call against its algorithmic bytes (one read of the grid for the
+    first pivot search, then per step one read and one write: the update pass
+    also scores the next step's candidates)."""
     f = torch.from_numpy(S.sphere_field(24, 0, n, m, L)).cuda()
     steps = 2 * L + 2
     for _ in range(max(1, args.warmup)):
@@ -436,8 +437,9 @@ def bench_ge(args, P, S, torch, np, n, m, L=12):
     rows = torch.arange(0, m, 97, device=f.device)
     rec = (c[:, rows].T * d[None, :]) @ r
     err = float((rec - f[rows]).abs().max() / f.abs().max())
-    # active steps: search (8 B per sample) + update (16 B); the step that stops the loop only searches
-    alg = n * m * (24 * active + (8 if active < steps else 0))
+    # one search before the first step (8 B per sample), then per active step one update pass that also
+    # scores the next step's candidates (16 B: read and write)
+    alg = n * m * (8 + 16 * active)
     log("bench: ge %.3f ms/call (%d steps, %d active), rel err %.2e, %.0f GB/s" % (ms, steps, active, err,
                                                                                     alg / (ms * 1e-3) / 1e9))
     return {"workload": "ge_lowrank_rank%d_n%d_m%d" % (2 * L + 1, n, m), "ms_per_call": ms, "steps": steps,

@@ -187,8 +187,9 @@ int sphere_poisson_eval_lowrank(sp_plan plan, int rank, const double* d, const d
  * zero-out step of eq. ZeroOut is not applied (the grid has no pole samples).
  * work: device workspace of sphere_poisson_ge_workspace_bytes(n, m) bytes
  * (the residual and the pivot search's partials), 16-byte aligned, as is r.
- * Each step is three launches on hip_stream: pivot search (one read of the
- * grid), pivot and factor extraction, rank-2 update (one read and write).
+ * One pivot search (one read of the grid) starts the loop; each step is then
+ * two launches on hip_stream: pivot and factor extraction, and the rank-2
+ * update fused with the next step's pivot search (one read and one write).
  * Errors: SP_ERR_INVALID_ARG (sizes, steps < 1, alpha outside [0, 1],
  * tol < 0, a NULL pointer, a small or misaligned workspace); SP_ERR_ALIAS
  * (outputs overlapping f, the workspace or each other); SP_ERR_HIP. */

@@ -8,10 +8,11 @@
 // The two rank-1 terms of a step are d (C0 +- C1)(R0 +- R1) with d = 1 / (2 (a +- b))
 // (0 where |a +- b| <= eps), C0 / C1 the residual's columns at lambda* - pi /
 // lambda*, R0 the row at theta* and R1 that row shifted by pi.
-// A step is three launches: partial pivot search, pivot + factor extraction
-// (one workgroup), and the rank-2 update of the residual (HBM-bound: one read
-// of the grid for the search, one read and write for the update); once the
-// loop has stopped, the remaining launches return at once.
+// A step is two launches: pivot + factor extraction (one workgroup), and the
+// rank-2 update of the residual fused with the next step's partial pivot
+// search (HBM-bound: one read and one write of the grid); one search pass
+// before the first step; once the loop has stopped, the remaining launches
+// return at once.
 // This translation unit is separate from the solver's: it owns no plan and
 // works in a workspace the caller provides.
 #include <hip/hip_runtime.h>
@@ -146,27 +147,46 @@ __global__ void __launch_bounds__(kGeThreads) k_ge_pivot(const double* __restric
     }
 }
 
-// 3. e -= d+ c+ r+^T + d- c- r-^T over the grid (two samples per thread step)
+// 3. e -= d+ c+ r+^T + d- c- r-^T over the grid, fused with the next step's
+// pivot search: each thread updates the pair of samples (lambda_i - pi,
+// lambda_i) of a row and scores the updated pair, so a step reads and writes
+// the grid once.  Rows go to workgroups as in k_ge_scores.
 __global__ void __launch_bounds__(kGeThreads) k_ge_update(double* __restrict__ e, int m, int n,
                                                          const double* __restrict__ d, const double* __restrict__ c,
-                                                         const double* __restrict__ r, int k) {
+                                                         const double* __restrict__ r, int k,
+                                                         const GeRecord* __restrict__ rec, double* __restrict__ pscore,
+                                                         long long* __restrict__ pidx) {
+    const int H = n / 2;
+    double best = -1.0;
+    long long bidx = 0x7fffffffffffffffLL;
+    if (rec->active == 0) {   // uniform: the loop has stopped, no candidate
+        if (threadIdx.x == 0) {
+            pscore[blockIdx.x] = best;
+            pidx[blockIdx.x] = bidx;
+        }
+        return;
+    }
     const double dp = d[2 * k], dm = d[2 * k + 1];
-    if (dp == 0.0 && dm == 0.0) return;   // uniform: every workgroup takes the same branch
     const double* cp = c + (size_t)(2 * k) * m;
     const double* cm = cp + m;
-    const double2* rp = reinterpret_cast<const double2*>(r + (size_t)(2 * k) * n);
-    const double2* rm = reinterpret_cast<const double2*>(r + (size_t)(2 * k + 1) * n);
-    const int H = n / 2;
-    const size_t total = (size_t)m * H;
-    double2* e2 = reinterpret_cast<double2*>(e);
-    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
-        const int t = (int)(q / H), l = (int)(q - (size_t)t * H);
+    const double* rp = r + (size_t)(2 * k) * n;
+    const double* rm = rp + n;
+    for (int t = blockIdx.x; t < m; t += gridDim.x) {
+        double* row = e + (size_t)t * n;
         const double ap = dp * cp[t], am = dm * cm[t];
-        const double2 p = rp[l], mi = rm[l];
-        double2 v = e2[q];
-        v.x -= ap * p.x + am * mi.x;
-        v.y -= ap * p.y + am * mi.y;
-        e2[q] = v;
+        for (int ih = threadIdx.x; ih < H; ih += blockDim.x) {
+            double e0 = row[ih], e1 = row[ih + H];
+            e0 -= ap * rp[ih] + am * rm[ih];
+            e1 -= ap * rp[ih + H] + am * rm[ih + H];
+            row[ih] = e0;
+            row[ih + H] = e1;
+            ge_better(fabs(e0) + fabs(e1), (long long)t * H + ih, best, bidx);
+        }
+    }
+    ge_block_argmax(best, bidx);
+    if (threadIdx.x == 0) {
+        pscore[blockIdx.x] = best;
+        pidx[blockIdx.x] = bidx;
     }
 }
 
@@ -232,16 +252,14 @@ extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double
     long long* pi = reinterpret_cast<long long*>(w + L.off_idx);
     spge::GeRecord* rec = reinterpret_cast<spge::GeRecord*>(w + L.off_rec);
     if (hipMemcpyAsync(e, f, fb, hipMemcpyDeviceToDevice, s) != hipSuccess) return SP_ERR_HIP;
-    const size_t pairs = (size_t)m * (n / 2);
-    const int ublocks = (int)((pairs + spge::kGeThreads - 1) / spge::kGeThreads < 4096
-                                  ? (pairs + spge::kGeThreads - 1) / spge::kGeThreads : 4096);
+    // the first search reads the grid; afterwards each update pass scores the next step's candidates
+    hipLaunchKernelGGL(spge::k_ge_scores, dim3(spge::kGeBlocks), dim3(spge::kGeThreads), 0, s, (const double*)e, m, n,
+                       (const spge::GeRecord*)rec, 0, ps, pi);
     for (int k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(spge::k_ge_scores, dim3(spge::kGeBlocks), dim3(spge::kGeThreads), 0, s, (const double*)e, m,
-                           n, (const spge::GeRecord*)rec, k, ps, pi);
         hipLaunchKernelGGL(spge::k_ge_pivot, dim3(1), dim3(spge::kGeThreads), 0, s, (const double*)e, m, n,
                            (const double*)ps, (const long long*)pi, spge::kGeBlocks, k, alpha, tol, rec, d, c, r, pivots);
-        hipLaunchKernelGGL(spge::k_ge_update, dim3(ublocks), dim3(spge::kGeThreads), 0, s, e, m, n, (const double*)d,
-                           (const double*)c, (const double*)r, k);
+        hipLaunchKernelGGL(spge::k_ge_update, dim3(spge::kGeBlocks), dim3(spge::kGeThreads), 0, s, e, m, n,
+                           (const double*)d, (const double*)c, (const double*)r, k, (const spge::GeRecord*)rec, ps, pi);
     }
     if (hipGetLastError() != hipSuccess) return SP_ERR_HIP;
     return SP_OK;
