@@ -188,8 +188,9 @@ int sphere_poisson_eval_lowrank(sp_plan plan, int rank, const double* d, const d
  * work: device workspace of sphere_poisson_ge_workspace_bytes(n, m) bytes
  * (the residual and the pivot search's partials), 16-byte aligned, as is r.
  * One pivot search (one read of the grid) starts the loop; each step is then
- * two launches on hip_stream: pivot and factor extraction, and the rank-2
- * update fused with the next step's pivot search (one read and one write).
+ * three launches on hip_stream: the pivot, the factor extraction, and the
+ * rank-2 update fused with the next step's pivot search (one read and one
+ * write of the grid).
  * Errors: SP_ERR_INVALID_ARG (sizes, steps < 1, alpha outside [0, 1],
  * tol < 0, a NULL pointer, a small or misaligned workspace); SP_ERR_ALIAS
  * (outputs overlapping f, the workspace or each other); SP_ERR_HIP. */

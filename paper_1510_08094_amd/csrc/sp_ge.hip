@@ -8,11 +8,11 @@
 // The two rank-1 terms of a step are d (C0 +- C1)(R0 +- R1) with d = 1 / (2 (a +- b))
 // (0 where |a +- b| <= eps), C0 / C1 the residual's columns at lambda* - pi /
 // lambda*, R0 the row at theta* and R1 that row shifted by pi.
-// A step is two launches: pivot + factor extraction (one workgroup), and the
-// rank-2 update of the residual fused with the next step's partial pivot
-// search (HBM-bound: one read and one write of the grid); one search pass
-// before the first step; once the loop has stopped, the remaining launches
-// return at once.
+// A step is three launches: the pivot (one workgroup), the factor extraction
+// (one thread per entry), and the rank-2 update of the residual fused with
+// the next step's partial pivot search (HBM-bound: one read and one write of
+// the grid); one search pass before the first step; once the loop has
+// stopped, the updates return at once.
 // This translation unit is separate from the solver's: it owns no plan and
 // works in a workspace the caller provides.
 #include <hip/hip_runtime.h>
@@ -30,6 +30,7 @@ constexpr int kGeThreads = 256;
 struct GeRecord {      // device state carried from step to step
     double s_first;    // sigma_1 of the first pivot
     int active;        // 0 once the loop has stopped
+    int t, i;          // this step's pivot (row, column with lambda_i in [0, pi))
 };
 
 // candidate (score, flat index t * (n/2) + i - n/2): larger score wins, ties go
@@ -88,20 +89,17 @@ __global__ void __launch_bounds__(kGeThreads) k_ge_scores(const double* __restri
     }
 }
 
-// 2. one workgroup: the pivot, its pseudoinverse, and the factors of step k
+// 2. one workgroup: the pivot and its pseudoinverse (d of step k)
 __global__ void __launch_bounds__(kGeThreads) k_ge_pivot(const double* __restrict__ e, int m, int n,
                                                         const double* __restrict__ pscore,
                                                         const long long* __restrict__ pidx, int nparts, int k,
                                                         double alpha, double tol, GeRecord* __restrict__ rec,
-                                                        double* __restrict__ d, double* __restrict__ c,
-                                                        double* __restrict__ r, int* __restrict__ piv) {
+                                                        double* __restrict__ d, int* __restrict__ piv) {
     const int H = n / 2;
     double best = -1.0;
     long long bidx = 0x7fffffffffffffffLL;
     for (int g = threadIdx.x; g < nparts; g += blockDim.x) ge_better(pscore[g], pidx[g], best, bidx);
     ge_block_argmax(best, bidx);
-    __shared__ double sh[2];
-    __shared__ int st[3];
     if (threadIdx.x == 0) {
         // no candidate at all (a residual of NaNs): stop, reading a valid point
         const bool found = bidx != 0x7fffffffffffffffLL;
@@ -112,42 +110,46 @@ __global__ void __launch_bounds__(kGeThreads) k_ge_pivot(const double* __restric
             rec->s_first = s1;
             rec->active = 1;
         }
-        int act = rec->active && s1 > 0.0 && !(s1 <= tol * rec->s_first);
+        const int act = rec->active && s1 > 0.0 && !(s1 <= tol * rec->s_first);
         rec->active = act;
+        rec->t = t;
+        rec->i = i;
         const double eps = alpha * s1;
-        sh[0] = act && fabs(a + b) > eps ? 1.0 / (a + b) : 0.0;
-        sh[1] = act && fabs(a - b) > eps ? 1.0 / (a - b) : 0.0;
-        st[0] = t;
-        st[1] = i;
-        st[2] = act;
+        const double gp = act && fabs(a + b) > eps ? 1.0 / (a + b) : 0.0;
+        const double gm = act && fabs(a - b) > eps ? 1.0 / (a - b) : 0.0;
         if (piv) {
             piv[2 * k] = act ? t : -1;
             piv[2 * k + 1] = act ? i : -1;
         }
-        d[2 * k] = 0.5 * sh[0];
-        d[2 * k + 1] = 0.5 * sh[1];
-    }
-    __syncthreads();
-    const int t = st[0], i = st[1], act = st[2];
-    double* cp = c + (size_t)(2 * k) * m;
-    double* cm = cp + m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const double c0 = act ? e[(size_t)j * n + i - H] : 0.0, c1 = act ? e[(size_t)j * n + i] : 0.0;
-        cp[j] = c0 + c1;
-        cm[j] = c0 - c1;
-    }
-    double* rp = r + (size_t)(2 * k) * n;
-    double* rm = rp + n;
-    const double* row = e + (size_t)t * n;
-    for (int l = threadIdx.x; l < n; l += blockDim.x) {
-        const int ls = l + H < n ? l + H : l - H;
-        const double r0 = act ? row[l] : 0.0, r1 = act ? row[ls] : 0.0;
-        rp[l] = r0 + r1;
-        rm[l] = r0 - r1;
+        d[2 * k] = 0.5 * gp;
+        d[2 * k + 1] = 0.5 * gm;
     }
 }
 
-// 3. e -= d+ c+ r+^T + d- c- r-^T over the grid, fused with the next step's
+// 3. the factors of step k, one thread per entry: c+- = C0 +- C1 (the columns
+// at lambda* - pi and lambda*), r+- = R0 +- R1 (the row at theta* and that row
+// shifted by pi); zeros once the loop has stopped
+__global__ void __launch_bounds__(kGeThreads) k_ge_extract(const double* __restrict__ e, int m, int n, int k,
+                                                          const GeRecord* __restrict__ rec, double* __restrict__ c,
+                                                          double* __restrict__ r) {
+    const int H = n / 2;
+    const int act = rec->active, t = rec->t, i = rec->i;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) {
+        const double c0 = act ? e[(size_t)q * n + i - H] : 0.0, c1 = act ? e[(size_t)q * n + i] : 0.0;
+        c[(size_t)(2 * k) * m + q] = c0 + c1;
+        c[(size_t)(2 * k + 1) * m + q] = c0 - c1;
+    } else if (q < m + n) {
+        const int l = q - m;
+        const int ls = l + H < n ? l + H : l - H;
+        const double* row = e + (size_t)t * n;
+        const double r0 = act ? row[l] : 0.0, r1 = act ? row[ls] : 0.0;
+        r[(size_t)(2 * k) * n + l] = r0 + r1;
+        r[(size_t)(2 * k + 1) * n + l] = r0 - r1;
+    }
+}
+
+// 4. e -= d+ c+ r+^T + d- c- r-^T over the grid, fused with the next step's
 // pivot search: each thread updates the pair of samples (lambda_i - pi,
 // lambda_i) of a row and scores the updated pair, so a step reads and writes
 // the grid once.  Rows go to workgroups as in k_ge_scores.
@@ -257,7 +259,9 @@ extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double
                        (const spge::GeRecord*)rec, 0, ps, pi);
     for (int k = 0; k < steps; ++k) {
         hipLaunchKernelGGL(spge::k_ge_pivot, dim3(1), dim3(spge::kGeThreads), 0, s, (const double*)e, m, n,
-                           (const double*)ps, (const long long*)pi, spge::kGeBlocks, k, alpha, tol, rec, d, c, r, pivots);
+                           (const double*)ps, (const long long*)pi, spge::kGeBlocks, k, alpha, tol, rec, d, pivots);
+        hipLaunchKernelGGL(spge::k_ge_extract, dim3((m + n + spge::kGeThreads - 1) / spge::kGeThreads),
+                           dim3(spge::kGeThreads), 0, s, (const double*)e, m, n, k, (const spge::GeRecord*)rec, c, r);
         hipLaunchKernelGGL(spge::k_ge_update, dim3(spge::kGeBlocks), dim3(spge::kGeThreads), 0, s, e, m, n,
                            (const double*)d, (const double*)c, (const double*)r, k, (const spge::GeRecord*)rec, ps, pi);
     }
