@@ -4,6 +4,9 @@ Definition pseudoinverse, lowrankRepresentationSplit): the pivot matrix's
 singular values, the eps-pseudoinverse against an SVD, one step annihilating
 the pivot rows and columns, exact recovery of fields of known rank, the
 paper's singular example f = 1, and the even/odd structure of the terms."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -95,3 +98,16 @@ def test_planted_unreflected_row(monkeypatch):
     d, C, R, piv, e = OG.ge_lowrank(f, 1, alpha=0.0)
     t, i = piv[0]
     assert max(np.max(np.abs(e[:, i])), np.max(np.abs(e[:, i - 5]))) > 1e-3
+
+
+def test_paper_rank_of_sin50xyz():
+    """The paper's Poisson example: sin(50xyz) on the 150 x 150 grid has
+    numerical rank 12 (tests/golden/sin50xyz_rank.json holds the citation);
+    the GE stops with 12 terms and a residual at the rounding level."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sin50xyz_rank.json")))
+    m, n = g["m_theta"], g["n_lambda"]
+    x, y, z = S.cartesian(n, m)
+    f = np.sin(50 * x * y * z)
+    d, C, R, piv, e = OG.ge_lowrank(f, 40, alpha=0.01, tol=1e-13)
+    assert np.count_nonzero(d) == g["paper_printed_rank"]
+    assert np.max(np.abs(e)) <= 1e-13 * np.max(np.abs(f))
