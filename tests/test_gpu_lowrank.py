@@ -159,3 +159,32 @@ def test_errors(P):
     plan.close()
     with pytest.raises(ValueError):
         P.SpherePoisson(n, m, "fp64").solve_lowrank(gpu(np.zeros(0)), gpu(np.zeros((0, m))), gpu(np.zeros((0, n))))
+
+
+@pytest.mark.parametrize("refine,low_k", [(2, -1), (2, 1), (0, -1)])
+def test_mixed_refinement_variants(P, refine, low_k):
+    """MIXED with two corrections (the second re-transforms u, never f), with
+    float32 elimination everywhere (two corrections needed), and with no
+    correction (float32 accuracy): the low-rank call follows the dense call."""
+    n, m, L = 256, 200, 20
+    d, C, R, u_exact = S.sphere_field_factors(18, L, n, m, L, with_solution=True)
+    plan = P.SpherePoisson(n, m, "mixed", max_refine=refine, low_k_fp64=low_k, sync_info=True)
+    u = host(plan.solve_lowrank(gpu(d), gpu(C), gpu(R)))
+    ud = host(plan.solve(gpu(OL.lowrank_grid(d, C, R))))
+    plan.close()
+    tol = TOL_MIXED if refine > 0 else 1e-5
+    assert rel2(u, u_exact) <= tol
+    assert rel2(u, ud) <= tol
+
+
+def test_eval_with_mixed_plan(P):
+    """Evaluation does not depend on the plan's precision (float64 tables)."""
+    n, m = 64, 48
+    d, C, R = S.lowrank_factors(19, 0, n, m, 6, 10)
+    pts = np.random.default_rng(5).standard_normal((300, 3))
+    outs = []
+    for prec in ("fp64", "mixed"):
+        plan = P.SpherePoisson(n, m, prec)
+        outs.append(host(plan.eval_lowrank(gpu(d), gpu(C), gpu(R), gpu(pts))))
+        plan.close()
+    assert rel2(outs[1], outs[0]) <= 1e-14
