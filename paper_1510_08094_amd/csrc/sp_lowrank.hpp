@@ -137,70 +137,102 @@ __global__ void __launch_bounds__(256) k_trig_coeffs(const double* __restrict__ 
     beta[(size_t)q * m + s] = b * (s == m - 1 ? 0.5 * w : w);
 }
 
-// One thread per point.  h: the lambda coefficients of the factors, already
-// multiplied by d_q and by the real-series weights (1 at k = 0 and k = n/2,
-// 2 between), contiguous rows of N + 1 values.
+// One Horner step p <- p w + a with the coefficient folded into the FMA chain
+// (four FMA-type instructions for a complex coefficient, four for a real one).
+__device__ __forceinline__ Cx<double> horner_c(Cx<double> p, Cx<double> w, Cx<double> a) {
+    return Cx<double>{fma(p.x, w.x, fma(-p.y, w.y, a.x)), fma(p.x, w.y, fma(p.y, w.x, a.y))};
+}
+__device__ __forceinline__ Cx<double> horner_r(Cx<double> p, Cx<double> w, double a) {
+    return Cx<double>{fma(p.x, w.x, fma(-p.y, w.y, a)), fma(p.x, w.y, p.y * w.x)};
+}
+
+// Two points per thread (kEvalPoints): the coefficient loads are uniform over
+// the workgroup and shared by both points, and the two points' chains are
+// independent.  h: the lambda coefficients of the factors, already multiplied
+// by d_q and by the real-series weights (1 at k = 0 and k = n/2, 2 between),
+// contiguous rows of N + 1 values.
+constexpr int kEvalPoints = 2;
+
 __global__ void __launch_bounds__(256) k_eval_lowrank(const double* __restrict__ alpha,
                                                       const double* __restrict__ beta,
                                                       const Cx<double>* __restrict__ h, int K, int m, int N,
                                                       const double* __restrict__ xyz, int npts,
                                                       double* __restrict__ out) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= npts) return;
-    const double x = xyz[3 * (size_t)p], y = xyz[3 * (size_t)p + 1], z = xyz[3 * (size_t)p + 2];
-    const double rho = sqrt(x * x + y * y + z * z);
-    // e^{i theta} = (z, sqrt(x^2 + y^2)) / rho; e^{i (lambda + pi)} = -e^{i lambda}, lambda = atan2(y, x)
-    const Cx<double> zt{fmin(fmax(z / rho, -1.0), 1.0), sqrt(x * x + y * y) / rho};
-    double sl, cl;
-    sincos(atan2(y, x), &sl, &cl);
-    const Cx<double> v{-cl, -sl};
-    const Cx<double> u = cmul(v, v);
-    double acc = 0.0;
+    const int p0 = (blockIdx.x * 256 + threadIdx.x) * kEvalPoints;
+    if (p0 >= npts) return;   // no barrier below
+    Cx<double> zt[kEvalPoints], v[kEvalPoints], u[kEvalPoints];
+    double acc[kEvalPoints];
+#pragma unroll
+    for (int e = 0; e < kEvalPoints; ++e) {
+        const int p = min(p0 + e, npts - 1);   // the last thread may repeat its point
+        const double x = xyz[3 * (size_t)p], y = xyz[3 * (size_t)p + 1], z = xyz[3 * (size_t)p + 2];
+        const double rho = sqrt(x * x + y * y + z * z);
+        // e^{i theta} = (z, sqrt(x^2 + y^2)) / rho; e^{i (lambda + pi)} = -e^{i lambda}, lambda = atan2(y, x)
+        zt[e] = Cx<double>{fmin(fmax(z / rho, -1.0), 1.0), sqrt(x * x + y * y) / rho};
+        double sl, cl;
+        sincos(atan2(y, x), &sl, &cl);
+        v[e] = Cx<double>{-cl, -sl};
+        u[e] = cmul(v[e], v[e]);
+        acc[e] = 0.0;
+    }
     for (int q = 0; q < K; ++q) {
         const double* aq = alpha + (size_t)q * m;
         const double* bq = beta + (size_t)q * m;
-        Cx<double> pe{0.0, 0.0}, po{0.0, 0.0};
+        Cx<double> pe[kEvalPoints], po[kEvalPoints];
+#pragma unroll
+        for (int e = 0; e < kEvalPoints; ++e) pe[e] = po[e] = Cx<double>{0.0, 0.0};
         int s = m - 1;
         for (; s >= 3; s -= 4) {   // four coefficients per scalar-load batch
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                pe = cmul(pe, zt);
-                po = cmul(po, zt);
-                pe.x += aq[s - e];
-                po.x += bq[s - e];
+            for (int j = 0; j < 4; ++j) {
+                const double a = aq[s - j], b = bq[s - j];
+#pragma unroll
+                for (int e = 0; e < kEvalPoints; ++e) {
+                    pe[e] = horner_r(pe[e], zt[e], a);
+                    po[e] = horner_r(po[e], zt[e], b);
+                }
             }
         }
         for (; s >= 0; --s) {
-            pe = cmul(pe, zt);
-            po = cmul(po, zt);
-            pe.x += aq[s];
-            po.x += bq[s];
+            const double a = aq[s], b = bq[s];
+#pragma unroll
+            for (int e = 0; e < kEvalPoints; ++e) {
+                pe[e] = horner_r(pe[e], zt[e], a);
+                po[e] = horner_r(po[e], zt[e], b);
+            }
         }
-        const double ce = pe.x;                    // sum alpha_s cos(s theta)
-        const double co = cmul(po, zt).y;          // sum beta_s sin((s + 1) theta)
-        const Cx<double>* hq = h + (size_t)q * (N + 1);
         // even terms h_{2j} and odd terms h_{2j+1} as polynomials in u; for even N
         // the top even term h_N has no odd partner and starts the even sum
-        Cx<double> pp{0.0, 0.0}, pm{0.0, 0.0};
+        const Cx<double>* hq = h + (size_t)q * (N + 1);
+        Cx<double> pp[kEvalPoints], pm[kEvalPoints];
         int k2 = N / 2;
-        if (!(N & 1)) {
-            pp = hq[N];
-            --k2;
+        const Cx<double> top = (N & 1) ? Cx<double>{0.0, 0.0} : hq[N];
+#pragma unroll
+        for (int e = 0; e < kEvalPoints; ++e) {
+            pp[e] = top;
+            pm[e] = Cx<double>{0.0, 0.0};
         }
+        if (!(N & 1)) --k2;
         for (; k2 >= 0; --k2) {
-            pp = cmul(pp, u);
-            pm = cmul(pm, u);
             const Cx<double> he = hq[2 * k2], ho = hq[2 * k2 + 1];
-            pp.x += he.x;
-            pp.y += he.y;
-            pm.x += ho.x;
-            pm.y += ho.y;
+#pragma unroll
+            for (int e = 0; e < kEvalPoints; ++e) {
+                pp[e] = horner_c(pp[e], u[e], he);
+                pm[e] = horner_c(pm[e], u[e], ho);
+            }
         }
-        const double rp = pp.x;                    // even wavenumbers
-        const double rm = cmul(pm, v).x;           // odd wavenumbers
-        acc += ce * rp + co * rm;
+#pragma unroll
+        for (int e = 0; e < kEvalPoints; ++e) {
+            const double ce = pe[e].x;                    // sum alpha_s cos(s theta)
+            const double co = cmul(po[e], zt[e]).y;       // sum beta_s sin((s + 1) theta)
+            const double rp = pp[e].x;                    // even wavenumbers
+            const double rm = cmul(pm[e], v[e]).x;        // odd wavenumbers
+            acc[e] += ce * rp + co * rm;
+        }
     }
-    out[p] = acc;
+#pragma unroll
+    for (int e = 0; e < kEvalPoints; ++e)
+        if (p0 + e < npts) out[p0 + e] = acc[e];
 }
 
 }  // namespace sp

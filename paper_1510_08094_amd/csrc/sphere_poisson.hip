@@ -1376,7 +1376,8 @@ extern "C" int sphere_poisson_eval_lowrank(sp_plan p, int rank, const double* d,
     }
     {
         ProfScope ps(p, SP_KERNEL_EVAL, s);
-        hipLaunchKernelGGL(sp::k_eval_lowrank, dim3(ceil_div(npts, 256)), dim3(256), 0, s, (const double*)alpha,
+        hipLaunchKernelGGL(sp::k_eval_lowrank, dim3(ceil_div(npts, 256 * sp::kEvalPoints)), dim3(256), 0, s,
+                           (const double*)alpha,
                            (const double*)beta, (const Cx<double>*)p->specB, rank, m, N, xyz, npts, out);
     }
     hipError_t e = hipGetLastError();
