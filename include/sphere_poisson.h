@@ -35,6 +35,15 @@
  *   SP_SYNC_INFO is set.  A plan must not be used by two streams at once
  *   (its workspace is shared by consecutive calls).
  *
+ * BEYOND THE SOLVE (each declared below with its passage)
+ *   Section 4 calculus on the same grid: tangential gradient, curl of a
+ *   scalar, surface divergence, curl and vorticity, and the integral over the
+ *   sphere.  Low-rank functions (Section 3, eq. lowrankRepresentation) given by
+ *   factor samples: the solve of such a right-hand side, pointwise evaluation
+ *   at arbitrary points, and their construction from samples by
+ *   structure-preserving Gaussian elimination (which owns no plan and works in
+ *   a workspace the caller provides).
+ *
  * ERRORS
  *   Every function returns an sp_status; nothing is printed, thrown or
  *   aborted across this boundary.  sphere_poisson_strerror() returns a static
