@@ -86,3 +86,40 @@ def test_binding_requires_library(monkeypatch, tmp_path):
     monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(P.LibraryMissing):
         P.library()
+
+
+def test_widened_calls_reject_null_plan(lib):
+    """The calculus, integration, low-rank and evaluation calls check the plan
+    before anything else."""
+    assert lib.sphere_poisson_tangential_gradient(None, None, None, None, None, None) == 8
+    assert lib.sphere_poisson_integral(None, None, None, None) == 8
+    assert lib.sphere_poisson_solve_lowrank(None, 3, None, None, None, None, 0.0, None, None) == 8
+    assert lib.sphere_poisson_eval_lowrank(None, 3, None, None, None, 10, None, None, None) == 8
+
+
+def test_ge_argument_validation(lib):
+    """The Gaussian-elimination constructor validates sizes, parameters,
+    pointers, workspace and aliasing before any device call (the pointers
+    below are never dereferenced)."""
+    n, m = 16, 12
+    wb = lib.sphere_poisson_ge_workspace_bytes(n, m)
+    assert wb >= n * m * 8
+    assert lib.sphere_poisson_ge_workspace_bytes(15, m) == 0
+    assert lib.sphere_poisson_ge_workspace_bytes(n, 0) == 0
+    vp = ctypes.c_void_p
+    f, work, d, c, r = 0x100000, 0x200000, 0x300000, 0x400000, 0x500000
+
+    def call(steps=2, alpha=0.01, tol=0.0, wbytes=wb, ff=f, ww=work, dd=d, cc=c, rr=r, nn=n):
+        return lib.sphere_poisson_ge_lowrank(nn, m, vp(ff), steps, alpha, tol, vp(ww), wbytes, vp(dd), vp(cc), vp(rr),
+                                             None, None)
+
+    assert call(steps=0) == 1
+    assert call(alpha=1.5) == 1 and call(alpha=-1e-3) == 1
+    assert call(tol=-1.0) == 1 and call(tol=float("nan")) == 1
+    assert call(nn=15) == 1
+    assert call(ff=None) == 1 and call(ww=None) == 1 and call(dd=None) == 1
+    assert call(wbytes=wb - 1) == 1
+    assert call(ww=work + 8) == 1 and call(rr=r + 8) == 1       # 16-byte alignment
+    assert call(cc=f) == 6                                         # output over the input
+    assert call(dd=work + 64) == 6                                 # output over the workspace
+    assert call(cc=r) == 6                                         # outputs over each other
