@@ -138,21 +138,28 @@ def test_errors(P):
     torch.cuda.synchronize()
 
 
-def test_paper_sin50xyz_rank_and_poisson(P):
-    """The paper's Poisson example, Delta u = sin(50xyz) on 150 x 150: the GE
-    finds the printed numerical rank 12 (tests/golden/sin50xyz_rank.json), and
-    the low-rank solve of its terms equals the oracle's solve of the samples.
-    Symmetric points of this function tie in exact arithmetic, so the pivot
-    order is not compared (either choice is valid)."""
-    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sin50xyz_rank.json")))
+@pytest.mark.parametrize("name", ["sin50xyz_rank.json", "sphere_test_func_rank.json"])
+def test_paper_printed_ranks_and_poisson(P, name):
+    """The paper's two printed numerical ranks on the grid of its Poisson
+    example (150 lambda nodes, 75 theta nodes): 12 for sin(50xyz) (Section 5)
+    and 23 for eq. sphereTestFunc (Section 1); tests/golden holds the
+    citations and the stopping tolerance.  The low-rank solve of the terms
+    equals the oracle's solve of the samples (eq. sphereTestFunc has a
+    non-zero mean: both sides solve the bordered system as it stands).  Symmetric points of these
+    functions can tie in exact arithmetic, so the pivot order is not compared
+    (either choice is valid)."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
     m, n = g["m_theta"], g["n_lambda"]
     x, y, z = S.cartesian(n, m)
-    f = np.sin(50 * x * y * z)
-    d, c, r, piv = P.ge_lowrank(gpu(f), 40, 0.01, 1e-13)
+    if g["paper_printed_rank"] == 12:
+        f = np.sin(50 * x * y * z)
+    else:
+        f = np.cos(1 + 2 * np.pi * (x + y) + 5 * np.sin(np.pi * z))
+    d, c, r, piv = P.ge_lowrank(gpu(f), 40, 0.01, 5e-13)
     dh = d.cpu().numpy()
     assert np.count_nonzero(dh) == g["paper_printed_rank"]
     rec = OL.lowrank_grid(dh, c.cpu().numpy(), r.cpu().numpy())
-    assert np.max(np.abs(rec - f)) <= 1e-13
+    assert np.max(np.abs(rec - f)) <= 1e-12 * np.max(np.abs(f))
     plan = P.SpherePoisson(n, m, "fp64")
     u = plan.solve_lowrank(d, c, r)
     torch.cuda.synchronize()
