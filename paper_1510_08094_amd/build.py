@@ -1,17 +1,26 @@
 """Build the HIP library in place: hipcc for gfx950 -> libsphere_poisson.so
-next to this file.  Run as ``python -m paper_1510_08094_amd.build``."""
+next to this file.  Each translation unit compiles to an object of its own,
+in parallel, and the objects link into the shared library.  Run as
+``python -m paper_1510_08094_amd.build``."""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-# the solver, and the Gaussian-elimination constructor in a translation unit of its own
-SRCS = [os.path.join(HERE, "csrc", "sphere_poisson.hip"), os.path.join(HERE, "csrc", "sp_ge.hip")]
+CSRC = os.path.join(HERE, "csrc")
+# the solver's host code and small kernels, the kernel builds of its passes (one unit per group),
+# and the Gaussian-elimination constructor
+SRCS = [os.path.join(CSRC, name) for name in (
+    "sphere_poisson.hip", "sp_inst_solve.hip", "sp_inst_mixed_small.hip", "sp_inst_mixed_large.hip",
+    "sp_inst_mixed_fixed.hip", "sp_inst_mixed_pick.hip", "sp_inst_batch_lambda.hip", "sp_inst_batch_theta64.hip",
+    "sp_inst_batch_theta_first.hip", "sp_inst_batch_theta_resid.hip", "sp_ge.hip")]
 OUT = os.path.join(HERE, "libsphere_poisson.so")
+OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 
@@ -23,21 +32,31 @@ def hipcc() -> str:
 
 
 def flags() -> list[str]:
-    return ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
+    return ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
             # packed FP32 instructions are kept out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + ["-o", tmp] + SRCS
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for %s" % " ".join(SRCS))
+        raise RuntimeError("hipcc failed: %s" % " ".join(cmd))
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    objs = [os.path.join(OBJDIR, os.path.basename(s)[:-4] + ".o") for s in SRCS]
+    cc = hipcc()
+    jobs = jobs or min(len(SRCS), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, [cc] + flags() + ["-c", s, "-o", o], verbose) for s, o in zip(SRCS, objs)]:
+            f.result()
+    tmp = OUT + ".tmp%d" % os.getpid()
+    _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, OUT)
     return OUT
 

@@ -160,12 +160,12 @@ __global__ void __launch_bounds__(NT, WPE) k_batch(const void* __restrict__ args
 }
 
 // Counters of every stage back to zero (a kernel node, not a memset node).
-__global__ void __launch_bounds__(64) k_batch_reset(int* counters, int n) {
+static __global__ void __launch_bounds__(64) k_batch_reset(int* counters, int n) {
     if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
 // One block per right-hand side: sums of the update partials -> scal[1], scal[2].
-__global__ void __launch_bounds__(256) k_batch_norms(const RhsDesc* __restrict__ descs, const int* __restrict__ nblk) {
+static __global__ void __launch_bounds__(256) k_batch_norms(const RhsDesc* __restrict__ descs, const int* __restrict__ nblk) {
     __shared__ double r0[256], r1[256];
     const RhsDesc& d = descs[blockIdx.x];
     const int nb = nblk[blockIdx.x];

@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(1024) k_lambda_grad(GradArgs a) {
 // First pass: workgroup b sums rows b, b + G, ... (a fixed order, so the
 // result is reproducible) into partial[b]; second pass: one workgroup adds
 // the partials.
-__global__ void __launch_bounds__(256) k_integral_rows(const double* __restrict__ f, const double* __restrict__ w,
+static __global__ void __launch_bounds__(256) k_integral_rows(const double* __restrict__ f, const double* __restrict__ w,
                                                        int n, int m, double* __restrict__ partial) {
     __shared__ Cx<double> red[8];
     double acc = 0.0;
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_integral_rows(const double* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(256) k_integral_total(const double* __restrict__ partial, int nb,
+static __global__ void __launch_bounds__(256) k_integral_total(const double* __restrict__ partial, int nb,
                                                         double* __restrict__ out) {
     __shared__ Cx<double> red[8];
     double acc = 0.0;

@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(1024) k_lambda_update(MixLambdaArgs a) {
 }
 
 // Sum of the per-block partials (one block): out[0] = sum of d^2, out[1] = sum of u^2.
-__global__ void __launch_bounds__(256) k_reduce_partials(const double* partial, int nblk, double* out) {
+static __global__ void __launch_bounds__(256) k_reduce_partials(const double* partial, int nblk, double* out) {
     __shared__ double r0[256], r1[256];
     double x = 0.0, y = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) { x += partial[2 * b]; y += partial[2 * b + 1]; }

@@ -24,9 +24,28 @@
 #include "sp_theta_real.hpp"
 #include "sp_calculus.hpp"
 #include "sp_lowrank.hpp"
+#include "sp_tables.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
+using sp::kEPT;
+using sp::kSmaxD;
+using sp::kSmaxF;
+using sp::kLayLog2;
+using sp::kSmaxR;
+using sp::kBatchThreads;
+using sp::kBatchClasses;
+using sp::kBatchSmallRadix;
+using sp::kBatchRealThreads;
+using sp::kBatchSmaxR;
+using sp::kBatchWaveThreads;
+using sp::KernelSet;
+using sp::MixedSet;
+using sp::BatchKernels;
+using sp::pick_kernels;
+using sp::pick_mixed;
+using sp::grad_kernel;
+using sp::batch_kernels;
 
 namespace {
 
@@ -43,11 +62,6 @@ int hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);     \
     } while (0)
 
-constexpr int kEPT = 16;
-constexpr int kSmaxD = 13;   // chunk rows per thread, float64 solves (odd: see make_class)
-constexpr int kSmaxF = 15;   // chunk rows per thread, float32 solves
-constexpr int kLayLog2 = 3;  // spectrum runs of 8 rows: one 128-byte line per float64 run
-constexpr int kSmaxR = 21;   // chunk rows per thread, real-part theta pass (both precisions)
 
 // ------------------------------------------------------------ twiddles
 // (cos, -sin)(2 pi t / N) in extended precision with exact quadrant
@@ -154,68 +168,6 @@ int solve_threads(int m, int smax) {
     return best;
 }
 
-// ------------------------------------------------------------ kernel table
-template <typename T>
-struct KernelSet {
-    void (*fwd)(sp::LambdaArgs<T>);
-    void (*inv)(sp::LambdaArgs<T>);
-    void (*theta)(sp::ThetaArgs<T>);        // complex line (odd m), float64 only
-    void (*theta_real)(sp::ThetaArgs<T>);   // one real part per workgroup (even m), float64 only
-};
-
-// RMAX: the radix set compiled into a kernel: 16 (radices up to 16), 32
-// (up to 31) or sp::kRadixFixed5000 (the fixed length-5000 transform).
-template <typename T, int RMAX>
-KernelSet<T> kernel_set() {
-    KernelSet<T> k{&sp::k_lambda_fwd<T, kEPT, RMAX>, &sp::k_lambda_inv<T, kEPT, RMAX>, nullptr, nullptr};
-    if constexpr (std::is_same<T, double>::value) {
-        if constexpr (RMAX != sp::kRadixFixed5000) k.theta = &sp::k_theta<double, kEPT, RMAX, kSmaxD>;
-        k.theta_real = &sp::k_theta_real<double, kEPT, RMAX, kSmaxR>;
-    }
-    return k;
-}
-
-void (*grad_kernel(int rs))(sp::GradArgs) {
-    if (rs == sp::kRadixFixed5000) return &sp::k_lambda_grad<kEPT, sp::kRadixFixed5000>;
-    return rs <= 16 ? &sp::k_lambda_grad<kEPT, 16> : &sp::k_lambda_grad<kEPT, 32>;
-}
-
-template <typename T>
-KernelSet<T> pick_kernels(int rs) {
-    if (rs == sp::kRadixFixed5000) return kernel_set<T, sp::kRadixFixed5000>();
-    return rs <= 16 ? kernel_set<T, 16>() : kernel_set<T, 32>();
-}
-
-struct MixedSet {
-    // [0] complex line (odd m), [1] one real part per workgroup (even m)
-    void (*theta_first[2])(sp::ThetaMixArgs);
-    void (*theta_resid[2])(sp::ThetaMixArgs);
-    void (*theta_first_t[2])(sp::ThetaMixArgs);   // transposed systems (adjoint)
-    void (*theta_resid_t[2])(sp::ThetaMixArgs);
-    void (*mix)(sp::MixLambdaArgs);
-    void (*update)(sp::MixLambdaArgs);
-};
-
-template <int RMAX>
-MixedSet mixed_set() {
-    MixedSet k{{nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, false, false>},
-               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, true, false>},
-               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, false, true>},
-               {nullptr, &sp::k_theta_mixed_real<kEPT, RMAX, kSmaxR, kSmaxR, true, true>},
-               &sp::k_lambda_mix<kEPT, RMAX>, &sp::k_lambda_update<kEPT, RMAX>};
-    if constexpr (RMAX != sp::kRadixFixed5000) {
-        k.theta_first[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, false>;
-        k.theta_resid[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, false>;
-        k.theta_first_t[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, false, true>;
-        k.theta_resid_t[0] = &sp::k_theta_mixed<kEPT, RMAX, kSmaxF, kSmaxD, true, true>;
-    }
-    return k;
-}
-
-MixedSet pick_mixed(int rs) {
-    if (rs == sp::kRadixFixed5000) return mixed_set<sp::kRadixFixed5000>();
-    return rs <= 16 ? mixed_set<16>() : mixed_set<32>();
-}
 
 // The radix set a transform needs (see kernel_set).
 int radix_set(const FftDesc& d, int nthr, bool fixed_ok) {
@@ -1582,7 +1534,6 @@ extern "C" int sphere_poisson_integral(sp_plan p, const double* f, double* out, 
 // ------------------------------------------------------------ batches
 namespace {
 
-constexpr int kBatchThreads = 256;
 constexpr size_t kBatchLamLds = 64 * 1024;   // LDS budget of a lambda tile (rows per tile follow)
 
 struct SizeTables {              // tables shared by every problem with the same n (or m)
@@ -1628,42 +1579,7 @@ BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebui
 // that stage's direction uses no radix above 16.  Small tiles keep more
 // wavenumbers in flight per compute unit; a line of m <= 2048 gives few
 // threads work in any phase.
-constexpr int kBatchClasses = 6;
-constexpr int kBatchSmallRadix = 16;
-constexpr int kBatchRealThreads = 128;
-constexpr int kBatchSmaxR = 17;    // chunk rows per thread in those tiles: the shortest that lets m = 2048 fit
-constexpr int kBatchWaveThreads = 64;
 
-struct BatchKernels {
-    void (*st[sp::kBStages][kBatchClasses])(const void*, const int2*, int, int*);
-};
-
-template <int STG>
-void batch_stage_kernels(BatchKernels& k) {
-    constexpr bool theta = STG == sp::kBTheta64 || STG == sp::kBThetaFirst || STG == sp::kBThetaResid;
-    k.st[STG][0] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxF, kSmaxD, STG, kBatchThreads, theta ? 3 : 4, false>;
-    k.st[STG][1] = &sp::k_batch<kEPT, 32, kSmaxF, kSmaxD, STG, kBatchThreads, 2, false>;
-    if constexpr (theta) {
-        k.st[STG][2] = &sp::k_batch<kEPT, kBatchSmallRadix, kBatchSmaxR, kBatchSmaxR, STG, kBatchRealThreads, 3, true>;
-        k.st[STG][3] = &sp::k_batch<kEPT, 32, kBatchSmaxR, kBatchSmaxR, STG, kBatchRealThreads, 2, true>;
-        k.st[STG][4] = &sp::k_batch<kEPT, kBatchSmallRadix, kSmaxR, kSmaxR, STG, kBatchWaveThreads, 3, true>;
-        k.st[STG][5] = &sp::k_batch<kEPT, 32, kSmaxR, kSmaxR, STG, kBatchWaveThreads, 2, true>;
-    } else {
-        for (int c = 2; c < kBatchClasses; ++c) k.st[STG][c] = nullptr;
-    }
-}
-
-BatchKernels batch_kernels() {
-    BatchKernels k;
-    batch_stage_kernels<sp::kBLamFwd>(k);
-    batch_stage_kernels<sp::kBTheta64>(k);
-    batch_stage_kernels<sp::kBLamInv>(k);
-    batch_stage_kernels<sp::kBThetaFirst>(k);
-    batch_stage_kernels<sp::kBLamMix>(k);
-    batch_stage_kernels<sp::kBThetaResid>(k);
-    batch_stage_kernels<sp::kBLamUpd>(k);
-    return k;
-}
 
 int radix_class(const std::vector<int>& rad) {
     for (int r : rad)
