@@ -112,6 +112,14 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true", help="skip timing the plain float64 solver")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem heterogeneous batch")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: radix orders by the fixed rule")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 16 x 2048^2 forward + adjoint measurement")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip the mixed solve with float32 eliminations for every k > 0 and two corrections")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the O(mn) size sweep")
+    ap.add_argument("--no-stream", action="store_true", help="skip the achievable-bandwidth kernels")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="only run the achievable-bandwidth kernels (copy, read, write of 10^8 doubles)")
     ap.add_argument("--no-gradient", action="store_true", help="skip the tangential-gradient measurement")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank right-hand side measurement")
     ap.add_argument("--no-eval", action="store_true", help="skip the pointwise-evaluation measurement")
@@ -128,6 +136,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args, torch)
+        return
+    if args.stream_only:
+        import paper_1510_08094_amd as P
+        print(json.dumps(bench_stream(args, P, torch)), flush=True)
         return
 
     import paper_1510_08094_amd as P
@@ -224,17 +236,10 @@ def main():
         u = None
 
     if not args.no_cpu_baseline:
-        import oracle as O
-        log("bench: timing the CPU oracle on the full workload")
-        t0 = time.perf_counter()
-        u_or = O.solve_reduced(f)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-                               "sample": "one full %dx%d solve (reduced-mode float64 oracle, numpy/scipy "
-                                         "single-threaded), %.1f s" % (n, m, dt),
-                               "host_cpus": os.cpu_count()}
+        out["cpu_baseline"], u_or = cpu_baseline(f, dof, n, m)
         if u is not None:
             out["rel_err_vs_oracle"] = float(np.linalg.norm(u - u_or) / np.linalg.norm(u_or))
+        del u_or
     plan.close()
     del fg, ug
     if not args.no_gradient:
@@ -245,9 +250,242 @@ def main():
         out["evaluation"] = bench_evaluate(args, P, S, torch, np)
     if not args.no_ge:
         out["ge"] = bench_ge(args, P, S, torch, np, n, m)
+    if not args.no_literal and args.precision == "mixed":
+        out["mixed_literal"] = bench_literal(args, P, torch, np, f, n, m, L, cfg)
+    del f
+    if not args.no_c4:
+        out["c4"] = bench_c4(args, P, S, torch, np)
+    if not args.no_sweep:
+        out["sweep"] = bench_sweep(args, P, S, torch, np)
+    if not args.no_stream:
+        out["achievable"] = bench_stream(args, P, torch)
+        out["roofline"]["frac_of_achievable"] = round(achieved / out["achievable"]["best_copy_GBps"], 4)
     if not args.no_batch:
         out["batch"] = bench_batch(args, P, S, torch, np)
     print(json.dumps(out), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(f, dof, n, m):
+    """The float64 oracle (reduced mode: numpy real FFT in lambda, scipy DCT /
+    DST in theta, banded solves vectorised over k) timed on this host: one
+    warm-up, then the median of three full solves, once with scipy.fft on every
+    core (workers = os.cpu_count(); numpy's FFT stays single-threaded) and once
+    on one core.  The thread count used is measured as process CPU time over
+    wall time."""
+    import resource
+    import statistics
+
+    import scipy.fft
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas = sorted({"%s:%d" % (i.get("internal_api", "?"), i.get("num_threads", 0)) for i in threadpool_info()})
+    except Exception:  # noqa: BLE001 - optional introspection
+        blas = []
+    cores = os.cpu_count() or 1
+    res = {}
+    u_or = None
+    for workers in (cores, 1):
+        times, cpu = [], []
+        with scipy.fft.set_workers(workers):
+            for rep in range(4):
+                r0 = resource.getrusage(resource.RUSAGE_SELF)
+                t0 = time.perf_counter()
+                u_or = O.solve_reduced(f)
+                dt = time.perf_counter() - t0
+                r1 = resource.getrusage(resource.RUSAGE_SELF)
+                if rep:
+                    times.append(dt)
+                    cpu.append((r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime))
+        med = statistics.median(times)
+        res[workers] = {"value": dof / med, "seconds": med, "cpu_seconds": statistics.median(cpu),
+                        "threads_used": round(statistics.median(cpu) / med, 2), "workers": workers}
+        log("bench: oracle with %d workers: %.2f s per solve (%.2f threads busy)" % (workers, med,
+                                                                                  res[workers]["threads_used"]))
+    allc = res[cores]
+    return ({"value": allc["value"], "unit": "DOF/s", "cores": cores, "kind": "oracle",
+             "sample": "full %dx%d float64 solves by the reduced-mode oracle, median of 3 after a warm-up, "
+                       "scipy.fft workers = %d (%.2f s each; process CPU time / wall time = %.2f)"
+                       % (n, m, cores, allc["seconds"], allc["threads_used"]),
+             "single_core": {"value": res[1]["value"], "unit": "DOF/s", "cores": 1, "seconds": res[1]["seconds"]},
+             "threads_used": allc["threads_used"], "cpu_model": cpu_model(), "blas_threads": blas,
+             "host_cpus": cores}, u_or)
+
+
+def bench_literal(args, P, torch, np, fg_host, n, m, L, cfg):
+    """The mixed solve with the literal precision split: float32 eliminations
+    for every k > 0 (only k = 0 in float64) and two corrections, on the same
+    workload: time per solve and error against the closed form (every 97th
+    row)."""
+    import sh_inputs as S
+    fg = torch.from_numpy(fg_host).cuda()
+    u = torch.empty_like(fg)
+    plan = P.SpherePoisson(n, m, "mixed", max_refine=2, low_k_fp64=1)
+    for _ in range(max(1, args.warmup)):
+        plan.solve(fg, out=u)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    steps = max(1, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(fg, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.close()
+    _, ue = S.sphere_field(cfg, 0, n, m, L, with_solution=True)
+    err = float(np.linalg.norm(u.cpu().numpy() - ue) / np.linalg.norm(ue))
+    log("bench: mixed literal (k >= 1 in float32, two corrections) %.3f ms/solve, rel err %.2e" % (ms, err))
+    return {"workload": "sphere_poisson_n%d_m%d_l%d_mixed_fp32_all_k_two_corrections" % (n, m, L),
+            "low_k_fp64": 1, "max_refine": 2, "ms_per_solve": ms, "dof_per_s": n * m / (ms * 1e-3),
+            "rel_err_vs_closed_form": err}
+
+
+def bench_c4(args, P, S, torch, np, count=16, n=2048, L=512):
+    """16 right-hand sides at n = m = 2048, loss sum ||u(f) - u_obs||^2 with
+    u_obs a seeded field l <= 512 plus N(0, 1e-3^2) noise: one step is the 16
+    forward solves and the 16 adjoint solves of the loss gradient (inputs and
+    the adjoint's right-hand sides resident).  Both precisions; the gradient
+    of the first problem is checked against the oracle's."""
+    import oracle as O
+    m = n
+    log("bench: synthesising the C4 problems")
+    fs = [S.sphere_field(4, r, n, m, L) for r in range(count)]
+    uobs = [S.sphere_field(4, r, n, m, L, tag=S.TAG_OBS) + S.noise(4, r, (m, n), 1e-3) for r in range(count)]
+    fg = [torch.from_numpy(a).cuda() for a in fs]
+    og = [torch.from_numpy(a).cuda() for a in uobs]
+    res = {"workload": "c4_16_rhs_n2048_m2048_forward_adjoint", "rhs": count, "dof_per_step": 2 * count * n * m}
+    for prec in ("fp64", "mixed"):
+        plan = P.SpherePoisson(n, m, prec)
+        us = [torch.empty_like(fg[0]) for _ in range(count)]
+        gs = []
+        for r in range(count):
+            plan.solve(fg[r], out=us[r])
+            gs.append(2.0 * (us[r] - og[r]))
+        fb = [torch.empty_like(fg[0]) for _ in range(count)]
+        torch.cuda.synchronize()
+
+        def step():
+            for r in range(count):
+                plan.solve(fg[r], out=us[r])
+            for r in range(count):
+                plan.adjoint(gs[r], out=fb[r])
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        steps = max(1, args.steps // 4)
+        plan.profile_enable(16 * count * steps)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        prof = plan.profile_read()
+        plan.profile_enable(0)
+        plan.close()
+        g0 = gs[0].cpu().numpy()
+        ref = O.adjoint_reduced(g0)
+        err = float(np.linalg.norm(fb[0].cpu().numpy() - ref) / np.linalg.norm(ref))
+        kern = {}
+        for k, (tot, cnt) in prof.items():
+            alg = kernel_bytes(k, n, m, prec)
+            avg = tot / cnt
+            kern[k] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": alg,
+                       "alg_GBps": round(alg / (avg * 1e-3) / 1e9, 1)}
+        log("bench: c4 %s %.3f ms/step (16 forward + 16 adjoint), gradient rel err %.2e" % (prec, ms, err))
+        res[prec] = {"ms_per_step": ms, "dof_per_s": res["dof_per_step"] / (ms * 1e-3), "kernels": kern,
+                     "gradient_rel_err_vs_oracle": err}
+        del us, gs, fb
+    return res
+
+
+def bench_sweep(args, P, S, torch, np, sizes=(1024, 2048, 4096, 10000)):
+    """Time per solve against the number of unknowns, n = m (the paper's
+    complexity experiment, Section 5, Figure FastSphericalPoissonSolver right):
+    both precisions, and the least-squares slope of log time against log(nm)."""
+    res = {"workload": "sweep_n_eq_m", "sizes": list(sizes)}
+    for prec in ("fp64", "mixed"):
+        ms_list = []
+        for n in sizes:
+            f = torch.from_numpy(S.sphere_field(5, n, n, n, n // 5)).cuda()
+            u = torch.empty_like(f)
+            plan = P.SpherePoisson(n, n, prec)
+            for _ in range(3):
+                plan.solve(f, out=u)
+            torch.cuda.synchronize()
+            reps = 20 if n < 10000 else 5
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                plan.solve(f, out=u)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_list.append(e0.elapsed_time(e1) / reps)
+            plan.close()
+            del f, u
+        x = np.log([float(n) * n for n in sizes])
+        y = np.log(ms_list)
+        slope = float(np.polyfit(x, y, 1)[0])
+        log("bench: sweep %s ms %s, slope %.3f" % (prec, ["%.3f" % t for t in ms_list], slope))
+        res[prec] = {"ms_per_solve": ms_list, "dof_per_s": [n * n / (t * 1e-3) for n, t in zip(sizes, ms_list)],
+                     "loglog_slope": slope}
+    return res
+
+
+def bench_stream(args, P, torch, count=10 ** 8):
+    """The library's streaming kernels (copy, read, write of 10^8 doubles,
+    plain and non-temporal) and torch's device copy: the achievable HBM
+    bandwidth the kernels' fractions are read against."""
+    dev = torch.device("cuda", 0)
+    x = torch.ones(count, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    part = torch.empty(int(P.library().sphere_poisson_stream_partials(count)), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {"workload": "stream_1e8_doubles", "doubles": count}
+
+    def timed(fn, nbytes):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return {"ms": round(ms, 5), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+    nb = count * 8
+    for nt in (False, True):
+        tag = "_nt" if nt else ""
+        res["copy" + tag] = timed(lambda: P.stream("copy", x, y, nt), 2 * nb)
+        res["read" + tag] = timed(lambda: P.stream("read", x, part, nt), nb)
+        res["write" + tag] = timed(lambda: P.stream("write", None, y, nt), nb)
+    res["torch_copy"] = timed(lambda: y.copy_(x), 2 * nb)
+    res["best_copy_GBps"] = max(res["copy"]["GBps"], res["copy_nt"]["GBps"])
+    log("bench: achievable bandwidth %s" % {k: v for k, v in res.items() if isinstance(v, dict)})
+    del x, y, part
+    return res
 
 
 def copy_calibration(args, torch):
@@ -457,21 +695,31 @@ def bench_batch(args, P, S, torch, np):
     us = [torch.empty_like(f) for f in fs]
     log("bench: batch inputs ready in %.1fs" % (time.time() - t0))
     dof = int(sum(int(n) * int(m) for n, m in sizes))
+    # the batch plan: radix orders of every distinct size from the autotuner (measured now when the
+    # cache has no entry), workspace, work lists and the captured graph; built once, outside the timing
+    t0 = time.time()
+    batch = P.SpherePoissonBatch(fs, us, "mixed", max_refine=1, autotune=not args.no_autotune)
+    plan_s = time.time() - t0
+    log("bench: batch plan built in %.1fs (autotune %s)" % (plan_s, not args.no_autotune))
     for _ in range(max(1, args.warmup)):
-        P.solve_batch(fs, "mixed", outs=us)
+        batch.solve()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     steps = max(1, args.steps // 4)
     e0.record(stream)
     for _ in range(steps):
-        P.solve_batch(fs, "mixed", outs=us)
+        batch.solve()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    _, infos = batch.solve(with_info=True)
+    batch.close()
     log("bench: batch %.3f ms/step, %.3e DOF/s" % (ms, dof / (ms * 1e-3)))
     return {"workload": "batch_512_rhs_n_m_uniform_128_2048_mixed", "rhs": 512, "dof": dof,
-            "ms_per_step": ms, "dof_per_s": dof / (ms * 1e-3), "launches_per_step": 1}
+            "ms_per_step": ms, "dof_per_s": dof / (ms * 1e-3), "launches_per_step": 1,
+            "autotuned": not args.no_autotune, "plan_seconds": plan_s,
+            "max_est_rel_err": max(i["est_rel_err"] for i in infos)}
 
 
 if __name__ == "__main__":

@@ -79,6 +79,8 @@ typedef enum {
 /* flags */
 #define SP_SYNC_INFO 0x1u   /* the solve synchronises `hip_stream` and fills *info (norms computed on device) */
 #define SP_AUTOTUNE 0x2u    /* plan: time candidate radix orders and row tiles for this size (cached, see below) */
+#define SP_INFO 0x4u        /* MIXED: compute the info norms on the device without waiting for them;
+                               sphere_poisson_get_info() reads them later */
 
 typedef struct {
     int n_lambda;       /* n: samples in lambda (even, >= 4) */
@@ -94,9 +96,17 @@ typedef struct {
 
 typedef struct {
     int iters;               /* refinement corrections applied (0 for FP64) */
-    double rel_correction;   /* ||last correction||_2 / ||u||_2 (MIXED), 0 for FP64 */
+    double rel_correction;   /* ||last correction||_2 / ||u||_2 on the grid (MIXED), 0 for FP64 */
     double f_integral;       /* quadrature of int f sin(theta) dtheta dlambda (exact for band-limited f) */
     int status;              /* sp_status of the call */
+    double rel_residual;     /* MIXED: ||F - (L - k^2) X||_2 / ||F||_2 over every wavenumber's theta
+                                coefficients (F: those of sin^2 f, X: those of the iterate the last
+                                correction was computed from; float64), 0 for FP64 */
+    double est_rel_err;      /* MIXED: estimated ||u - u_exact||_2 / ||u||_2 of the returned u, where
+                                u_exact solves the discrete system: the last relative correction times
+                                the contraction the corrections show (the ratio of the last two, or
+                                with one correction the relative size of that correction itself, which
+                                is the float32 solve's own relative error); 0 for FP64 */
 } sp_info;
 
 typedef struct sp_plan_s* sp_plan;
@@ -123,7 +133,8 @@ int sphere_poisson_plan(sp_plan* out, const sp_desc* desc, void* hip_stream);
  * doubled-up half domain (the constraint row of the k = 0 system).
  * f is not required to have zero mean (the paper's precondition); the
  * bordered k = 0 system is solved as is and info->f_integral reports the
- * mean.  `info` may be NULL; it is filled only with SP_SYNC_INFO.
+ * mean.  `info` may be NULL; it is filled only with SP_SYNC_INFO (or later by
+ * sphere_poisson_get_info).
  * MIXED plans also use u as scratch between their kernels (the float32 first
  * iterate is kept there until the update pass overwrites it), so u holds the
  * solution only once the stream reaches the end of the solve.
@@ -210,27 +221,83 @@ int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int st
 
 /* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
  * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
- * for any loss; same layout, ownership and errors as sphere_poisson_solve. */
+ * for any loss; same layout, ownership and errors as sphere_poisson_solve.
+ * A MIXED adjoint applies at most one correction (its iterate is refined
+ * without sin^2, whose coefficients are recovered from the transform of the
+ * iterate itself): a plan with max_refine > 1 gives SP_ERR_INVALID_ARG. */
 int sphere_poisson_solve_adjoint(sp_plan plan, const double* g, double* fbar,
                                  void* hip_stream, sp_info* info);
 
-/* Solve `count` independent problems of possibly different sizes with one
- * launch of a HIP graph (one persistent kernel per solve stage and kernel
- * build, each taking (problem, tile) items from a work list).  n[r], m[r]:
- * sizes of problem r (host arrays); f[r], u[r]: device pointers (host arrays
- * of pointers), each [m[r]][n[r]] float64; every problem uses integral = 0.
- * The batch plan (workspace, schedules per distinct size, graph) is built on
- * the first call for a given size list and reused while the list and the
- * pointers are unchanged.  In SP_MIXED, u[r] is scratch until the graph ends,
- * as in sphere_poisson_solve.  `infos` may be NULL (else `count` entries;
- * filled after a synchronisation of `hip_stream`).
- * Every problem must fit the batch tiles (256 threads): n/2 up to about 4096
- * and m up to about 3300 (the exact bounds depend on the radices);
- * SP_ERR_UNSUPPORTED_SIZE otherwise.
- * Errors: as sphere_poisson_plan and sphere_poisson_solve. */
-int sphere_poisson_solve_batch(int count, const int* n, const int* m,
-                               const double* const* f, double* const* u,
-                               int precision, void* hip_stream, sp_info* infos);
+/* Heterogeneous batches (spec change 2: many right-hand sides of uneven
+ * grid sizes solved by one persistent, graph-captured launch; the paper notes
+ * the solver is embarrassingly parallel, Section 5).
+ *
+ * sphere_poisson_batch_plan builds a batch plan for `count` problems:
+ * n[r], m[r]: sizes of problem r (host arrays); f[r], u[r]: device pointers
+ * (host arrays of pointers), each [m[r]][n[r]] float64, bound to the plan.
+ * desc: precision, max_refine (MIXED: 1..4 corrections), tol and flags
+ * (SP_AUTOTUNE: measure the radix orders of every distinct size first, as
+ * for sphere_poisson_plan); n_lambda, m_theta and low_k_fp64 are ignored
+ * (each problem eliminates k < max(16, m/64) in float64 in MIXED).  The plan
+ * allocates every problem's workspace and tables, builds the work lists
+ * (one item per lambda row block or theta tile, longest first) and captures
+ * the HIP graph: a counter reset kernel, then per solve stage one persistent
+ * kernel per kernel build with work, each taking (problem, tile) items from
+ * its list; with max_refine = R the correction stages run R times.  Every
+ * problem uses integral = 0.  Every problem must fit the batch tiles (256
+ * threads): n/2 up to about 4096 and m up to about 3300 (the exact bounds
+ * depend on the radices), else SP_ERR_UNSUPPORTED_SIZE.
+ * No u[r] may overlap another problem's f or u, nor its own f (SP_ERR_ALIAS;
+ * f buffers may be shared); in SP_MIXED u[r] is scratch until the graph
+ * ends, as in sphere_poisson_solve.
+ * Errors: SP_ERR_INVALID_ARG (count <= 0, a NULL pointer, bad sizes or
+ * precision, max_refine outside 1..4 in MIXED), SP_ERR_ALIAS,
+ * SP_ERR_UNSUPPORTED_SIZE, SP_ERR_OOM, SP_ERR_HIP, SP_ERR_NO_DEVICE.
+ *
+ * sphere_poisson_solve_batch launches the graph once on `hip_stream`; it
+ * allocates nothing.  The data is read from and written to the buffers bound
+ * at planning.  `infos` may be NULL (else `count` entries, filled after a
+ * synchronisation of `hip_stream`: iters, rel_correction, est_rel_err and
+ * f_integral per problem, rel_residual is not computed in a batch (0)).
+ * With tol > 0 a MIXED problem whose last relative correction exceeds tol
+ * gets status SP_ERR_NOT_CONVERGED in its info, and the call returns that
+ * code (only when infos is given: the check needs the synchronisation).
+ * Calls on one batch plan must not overlap (they share its workspace and
+ * counters).  Errors: SP_ERR_BAD_PLAN, SP_ERR_HIP, SP_ERR_NOT_CONVERGED.
+ *
+ * sphere_poisson_batch_destroy waits for the plan's last launch and releases
+ * it. */
+typedef struct sp_batch_s* sp_batch;
+int sphere_poisson_batch_plan(sp_batch* out, int count, const int* n, const int* m, const double* const* f,
+                              double* const* u, const sp_desc* desc, void* hip_stream);
+int sphere_poisson_solve_batch(sp_batch batch, void* hip_stream, sp_info* infos);
+int sphere_poisson_batch_destroy(sp_batch batch);
+
+/* The info of the plan's last solve (or adjoint): synchronises `hip_stream`
+ * and fills *info as SP_SYNC_INFO would have.  The norms (rel_correction,
+ * rel_residual, est_rel_err) exist only when the plan has SP_SYNC_INFO or
+ * SP_INFO in its flags; otherwise they read -1.  status is the last call's
+ * return value, with SP_ERR_NOT_CONVERGED applied as for SP_SYNC_INFO.
+ * Errors: SP_ERR_BAD_PLAN, SP_ERR_INVALID_ARG (info NULL), SP_ERR_HIP. */
+int sphere_poisson_get_info(sp_plan plan, void* hip_stream, sp_info* info);
+
+/* Diagnostic: the achievable HBM bandwidth of the device, the ceiling
+ * against which the solver's kernels are read (no passage of the paper: the
+ * roofline of the measurement).  kind = SP_STREAM_COPY (y[i] = x[i]),
+ * SP_STREAM_READ (every element of x read once; y receives one partial sum per
+ * workgroup, sphere_poisson_stream_partials(count) doubles) or SP_STREAM_WRITE
+ * (y[i] = 1; x unused, may be NULL), optionally | SP_STREAM_NONTEMPORAL
+ * (non-temporal loads and stores).  count: doubles; x, y device pointers,
+ * 16-byte aligned; each workgroup moves one contiguous 16 KiB chunk with
+ * 128-bit accesses.  Asynchronous on hip_stream; count = 0 does nothing.
+ * Errors: SP_ERR_INVALID_ARG (kind, a NULL or misaligned pointer),
+ * SP_ERR_ALIAS (y overlapping x), SP_ERR_UNSUPPORTED_SIZE, SP_ERR_HIP. */
+#define SP_STREAM_COPY 0
+#define SP_STREAM_READ 1
+#define SP_STREAM_WRITE 2
+#define SP_STREAM_NONTEMPORAL 0x10
+size_t sphere_poisson_stream_partials(size_t count);
+int sphere_poisson_stream(int kind, const double* x, double* y, size_t count, void* hip_stream);
 
 /* Release every resource of a plan (waits for its pending work). */
 int sphere_poisson_destroy(sp_plan plan);

@@ -15,16 +15,19 @@ import re
 
 import torch  # loads the HIP runtime that the library then shares
 
-__all__ = ["SpherePoisson", "SpherePoissonFunction", "solve_batch", "library", "LibraryMissing",
-           "SP_FP64", "SP_MIXED", "SP_SYNC_INFO", "SP_AUTOTUNE", "SpError", "exported_symbols"]
+__all__ = ["SpherePoisson", "SpherePoissonFunction", "SpherePoissonBatch", "solve_batch", "library",
+           "LibraryMissing", "SP_FP64", "SP_MIXED", "SP_SYNC_INFO", "SP_AUTOTUNE", "SP_INFO", "SpError",
+           "exported_symbols"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsphere_poisson.so")
+# SPHERE_POISSON_LIB selects another build of the same library (the host-sanitizer build of the CPU checks)
+LIB_PATH = os.environ.get("SPHERE_POISSON_LIB") or os.path.join(_HERE, "libsphere_poisson.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "sphere_poisson.h")
 
 SP_FP64, SP_MIXED = 0, 1
 SP_SYNC_INFO = 0x1
 SP_AUTOTUNE = 0x2
+SP_INFO = 0x4
 _STATUS = {0: "SP_OK", 1: "SP_ERR_INVALID_ARG", 2: "SP_ERR_UNSUPPORTED_SIZE", 3: "SP_ERR_OOM",
            4: "SP_ERR_HIP", 5: "SP_ERR_NOT_CONVERGED", 6: "SP_ERR_ALIAS", 7: "SP_ERR_NO_DEVICE",
            8: "SP_ERR_BAD_PLAN"}
@@ -48,7 +51,11 @@ class SpDesc(ctypes.Structure):
 
 class SpInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rel_correction", ctypes.c_double),
-                ("f_integral", ctypes.c_double), ("status", ctypes.c_int)]
+                ("f_integral", ctypes.c_double), ("status", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("est_rel_err", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -79,9 +86,14 @@ def library():
     lib.sphere_poisson_ge_workspace_bytes.argtypes = [ci, ci]
     lib.sphere_poisson_ge_workspace_bytes.restype = ctypes.c_size_t
     lib.sphere_poisson_ge_lowrank.argtypes = [ci, ci, vp, ci, cd, cd, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
-    lib.sphere_poisson_solve_batch.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
-                                               ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp,
-                                               ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_batch_plan.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SpDesc), vp]
+    lib.sphere_poisson_solve_batch.argtypes = [vp, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_batch_destroy.argtypes = [vp]
+    lib.sphere_poisson_get_info.argtypes = [vp, vp, ctypes.POINTER(SpInfo)]
+    lib.sphere_poisson_stream.argtypes = [ci, vp, vp, ctypes.c_size_t, vp]
+    lib.sphere_poisson_stream_partials.argtypes = [ctypes.c_size_t]
+    lib.sphere_poisson_stream_partials.restype = ctypes.c_size_t
     lib.sphere_poisson_destroy.argtypes = [vp]
     lib.sphere_poisson_strerror.argtypes = [ci]
     lib.sphere_poisson_strerror.restype = ctypes.c_char_p
@@ -97,7 +109,8 @@ def library():
     lib.sphere_poisson_profile_enable.argtypes = [vp, ci]
     lib.sphere_poisson_profile_read.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
     for name in ("sphere_poisson_profile_enable", "sphere_poisson_profile_read", "sphere_poisson_plan", "sphere_poisson_solve", "sphere_poisson_solve_adjoint",
-                 "sphere_poisson_solve_batch", "sphere_poisson_destroy",
+                 "sphere_poisson_solve_batch", "sphere_poisson_destroy", "sphere_poisson_batch_plan",
+                 "sphere_poisson_batch_destroy", "sphere_poisson_get_info", "sphere_poisson_stream",
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
                  "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank",
@@ -131,14 +144,16 @@ class SpherePoisson:
     """A plan for one grid size and precision (owns the device workspace)."""
 
     def __init__(self, n: int, m: int, precision: str = "fp64", max_refine: int = 1, tol: float = 0.0,
-                 sync_info: bool = False, device=None, low_k_fp64: int = -1, autotune: bool = False):
+                 sync_info: bool = False, device=None, low_k_fp64: int = -1, autotune: bool = False,
+                 collect_info: bool = False):
         lib = library()
         self.n, self.m = int(n), int(m)
         self.precision = {"fp64": SP_FP64, "mixed": SP_MIXED}[precision]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.desc = SpDesc(self.n, self.m, self.precision, int(max_refine), float(tol),
-                           (SP_SYNC_INFO if sync_info else 0) | (SP_AUTOTUNE if autotune else 0),
+                           (SP_SYNC_INFO if sync_info else 0) | (SP_AUTOTUNE if autotune else 0) |
+                           (SP_INFO if collect_info else 0),
                            int(low_k_fp64))
         self._plan = ctypes.c_void_p()
         self.info = SpInfo()
@@ -211,6 +226,14 @@ class SpherePoisson:
                                                           ctypes.c_void_p(_stream_handle(self.device)),
                                                           ctypes.byref(self.info)))
         return fb
+
+    def get_info(self) -> dict:
+        """The info of the last solve or adjoint (synchronises the stream)."""
+        info = SpInfo()
+        with torch.cuda.device(self.device):
+            _check(library().sphere_poisson_get_info(self._plan, ctypes.c_void_p(_stream_handle(self.device)),
+                                                     ctypes.byref(info)))
+        return info.as_dict()
 
     def roundtrip(self, f: torch.Tensor) -> torch.Tensor:
         _check_grid(f, self.m, self.n, "f")
@@ -341,22 +364,76 @@ def ge_lowrank(f: torch.Tensor, steps: int, alpha: float = 0.01, tol: float = 0.
     return d, c, r, piv
 
 
-def solve_batch(fs, precision: str = "mixed", outs=None):
-    """Solve every f in `fs` (list of [m_r, n_r] float64 CUDA tensors) in one call."""
+STREAM_KINDS = {"copy": 0, "read": 1, "write": 2}
+
+
+def stream(kind: str, x: torch.Tensor | None, y: torch.Tensor, nontemporal: bool = False):
+    """The achievable-bandwidth kernels (sphere_poisson_stream): kind "copy"
+    (y = x), "read" (y receives per-workgroup partial sums of x) or "write"
+    (y = 1), on float64 device tensors."""
     lib = library()
-    count = len(fs)
-    ns = (ctypes.c_int * count)(*[int(f.shape[1]) for f in fs])
-    ms = (ctypes.c_int * count)(*[int(f.shape[0]) for f in fs])
-    us = [torch.empty_like(f) for f in fs] if outs is None else outs
-    for f, u in zip(fs, us):
-        _check_grid(f, f.shape[0], f.shape[1], "f")
-        _check_grid(u, f.shape[0], f.shape[1], "out")
-    fp = (ctypes.c_void_p * count)(*[f.data_ptr() for f in fs])
-    up = (ctypes.c_void_p * count)(*[u.data_ptr() for u in us])
-    infos = (SpInfo * count)()
-    dev = fs[0].device
+    count = y.numel() if kind != "read" else x.numel()
+    code = STREAM_KINDS[kind] | (0x10 if nontemporal else 0)
+    dev = y.device
     with torch.cuda.device(dev):
-        _check(lib.sphere_poisson_solve_batch(count, ns, ms, fp, up,
-                                              {"fp64": SP_FP64, "mixed": SP_MIXED}[precision],
-                                              ctypes.c_void_p(_stream_handle(dev)), infos))
+        _check(lib.sphere_poisson_stream(code, ctypes.c_void_p(x.data_ptr() if x is not None else 0),
+                                         ctypes.c_void_p(y.data_ptr()), count,
+                                         ctypes.c_void_p(_stream_handle(dev))))
+
+
+class SpherePoissonBatch:
+    """A batch plan: the problems fs (list of [m_r, n_r] float64 CUDA tensors)
+    and their outputs are bound to it; every solve() is one graph launch."""
+
+    def __init__(self, fs, outs=None, precision: str = "mixed", max_refine: int = 1, tol: float = 0.0,
+                 autotune: bool = False):
+        lib = library()
+        self.count = count = len(fs)
+        self.fs = list(fs)
+        self.us = [torch.empty_like(f) for f in fs] if outs is None else list(outs)
+        for f, u in zip(self.fs, self.us):
+            _check_grid(f, f.shape[0], f.shape[1], "f")
+            _check_grid(u, f.shape[0], f.shape[1], "out")
+        ns = (ctypes.c_int * count)(*[int(f.shape[1]) for f in fs])
+        ms = (ctypes.c_int * count)(*[int(f.shape[0]) for f in fs])
+        fp = (ctypes.c_void_p * count)(*[f.data_ptr() for f in self.fs])
+        up = (ctypes.c_void_p * count)(*[u.data_ptr() for u in self.us])
+        desc = SpDesc(0, 0, {"fp64": SP_FP64, "mixed": SP_MIXED}[precision], int(max_refine), float(tol),
+                      SP_AUTOTUNE if autotune else 0, -1)
+        self.device = self.fs[0].device
+        self._plan = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.sphere_poisson_batch_plan(ctypes.byref(self._plan), count, ns, ms, fp, up, ctypes.byref(desc),
+                                                 ctypes.c_void_p(_stream_handle(self.device))))
+        self.infos = (SpInfo * count)()
+
+    def solve(self, with_info: bool = False):
+        """Launch the graph; returns the outputs (and the per-problem infos)."""
+        with torch.cuda.device(self.device):
+            code = library().sphere_poisson_solve_batch(self._plan, ctypes.c_void_p(_stream_handle(self.device)),
+                                                        self.infos if with_info else None)
+        if code != 0 and not (with_info and code == 5):
+            _check(code)
+        if with_info:
+            return self.us, [self.infos[r].as_dict() for r in range(self.count)]
+        return self.us
+
+    def close(self):
+        if self._plan:
+            _check(library().sphere_poisson_batch_destroy(self._plan))
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(fs, precision: str = "mixed", outs=None, max_refine: int = 1):
+    """Solve every f in `fs` (list of [m_r, n_r] float64 CUDA tensors) with a
+    batch plan built for the call."""
+    b = SpherePoissonBatch(fs, outs, precision, max_refine)
+    us = b.solve()
+    b.close()
     return us

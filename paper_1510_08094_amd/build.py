@@ -47,19 +47,33 @@ def _run(cmd: list[str], verbose: bool) -> None:
         raise RuntimeError("hipcc failed: %s" % " ".join(cmd))
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
-    objs = [os.path.join(OBJDIR, os.path.basename(s)[:-4] + ".o") for s in SRCS]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the CPU checks
+# of the C ABI (argument validation, plan and batch-plan bookkeeping): each
+# -fsanitize applies to the host compilation only; the device code is built as
+# usual.  The result is a separate library that only CPU tests load (with the
+# sanitizer runtime preloaded, see README).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+OUT_SANITIZE = os.path.join(OBJDIR, "libsphere_poisson_asan.so")
+
+
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False) -> str:
+    objdir = os.path.join(OBJDIR, "asan") if sanitize else OBJDIR
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(s)[:-4] + ".o") for s in SRCS]
     cc = hipcc()
+    extra = SANITIZE if sanitize else []
     jobs = jobs or min(len(SRCS), max(1, min(8, os.cpu_count() or 1)))
     with ThreadPoolExecutor(jobs) as ex:
-        for f in [ex.submit(_run, [cc] + flags() + ["-c", s, "-o", o], verbose) for s, o in zip(SRCS, objs)]:
+        for f in [ex.submit(_run, [cc] + flags() + extra + ["-c", s, "-o", o], verbose)
+                  for s, o in zip(SRCS, objs)]:
             f.result()
-    tmp = OUT + ".tmp%d" % os.getpid()
-    _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, OUT)
-    return OUT
+    out = OUT_SANITIZE if sanitize else OUT
+    tmp = out + ".tmp%d" % os.getpid()
+    _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + extra + ["-o", tmp] + objs, verbose)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv[1:]))

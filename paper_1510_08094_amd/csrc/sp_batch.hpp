@@ -38,7 +38,7 @@ struct RhsDesc {
     const double* sin2;
     const double* k0tab;
     const double* fint_w;
-    double* scal;      // [0] integral of f, [1] sum d^2, [2] sum u^2
+    double* scal;      // [0] integral of f, then per correction it: [2 it - 1] sum d^2, [2 it] sum u^2
     double* partial;   // 2 per lambda block
 };
 
@@ -164,8 +164,9 @@ static __global__ void __launch_bounds__(64) k_batch_reset(int* counters, int n)
     if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
-// One block per right-hand side: sums of the update partials -> scal[1], scal[2].
-static __global__ void __launch_bounds__(256) k_batch_norms(const RhsDesc* __restrict__ descs, const int* __restrict__ nblk) {
+// One block per right-hand side: sums of the update partials -> scal[slot], scal[slot + 1].
+static __global__ void __launch_bounds__(256) k_batch_norms(const RhsDesc* __restrict__ descs, const int* __restrict__ nblk,
+                                                            int slot) {
     __shared__ double r0[256], r1[256];
     const RhsDesc& d = descs[blockIdx.x];
     const int nb = nblk[blockIdx.x];
@@ -178,7 +179,7 @@ static __global__ void __launch_bounds__(256) k_batch_norms(const RhsDesc* __res
         if ((int)threadIdx.x < h) { r0[threadIdx.x] += r0[threadIdx.x + h]; r1[threadIdx.x] += r1[threadIdx.x + h]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) { d.scal[1] = r0[0]; d.scal[2] = r1[0]; }
+    if (threadIdx.x == 0) { d.scal[slot] = r0[0]; d.scal[slot + 1] = r1[0]; }
 }
 
 }  // namespace sp

@@ -235,9 +235,31 @@ __device__ __forceinline__ void dft_odd_store(Cx<T>* v, Cx<T>* __restrict__ out,
     }
 }
 
+// R = 10 as 2 x 5 by the prime-factor (Good-Thomas) mapping, no twiddles:
+// input n = (5 n1 + 2 n2) mod 10, output k = (5 k1 + 6 k2) mod 10; two DFT5
+// over n2, then five DFT2 over n1.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft10(Cx<T>* v) {
+    Cx<T> a[5], b[5];
+#pragma unroll
+    for (int n2 = 0; n2 < 5; ++n2) {
+        a[n2] = v[(2 * n2) % 10];
+        b[n2] = v[(5 + 2 * n2) % 10];
+    }
+    dft_odd<T, 5, INV>(a);
+    dft_odd<T, 5, INV>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < 5; ++k2) {
+        v[(6 * k2) % 10] = a[k2] + b[k2];
+        v[(5 + 6 * k2) % 10] = a[k2] - b[k2];
+    }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft(Cx<T>* v) {
-    if constexpr (R == 2) {
+    if constexpr (R == 10) {
+        dft10<T, INV>(v);
+    } else if constexpr (R == 2) {
         dft2<T, INV>(v[0], v[1]);
     } else if constexpr (R == 4) {
         dft4<T, INV>(v[0], v[1], v[2], v[3]);
@@ -383,7 +405,10 @@ __device__ __forceinline__ void fft_ct_passes(Cx<T>* __restrict__ buf, const Cx<
 // count match.
 enum FixedFft { kFixedNone = 0, kFixed5000 = 1 };
 constexpr int kRadixFixed5000 = -5000;
-constexpr int kFixed5000Threads = 334;   // 5000 = 5^4 8: radix-5 passes with 3 butterflies per thread
+// 5000 = 5 10^3: a radix-5 pass (two butterflies per thread), then three
+// radix-10 passes with one butterfly per thread
+constexpr int kFixed5000Threads = 500;
+constexpr int kFixed5000Radices[4] = {5, 10, 10, 10};
 
 // Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
 // radices compiled into this instantiation.
@@ -394,7 +419,7 @@ __device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ base, int off, const
     if constexpr (RMAX == kRadixFixed5000) {
         (void)d;
         (void)nthr;
-        fft_ct_passes<T, INV, 5000, kFixed5000Threads, 1, 5, 5, 5, 5, 8>(base + off, ptw, t0, active);
+        fft_ct_passes<T, INV, 5000, kFixed5000Threads, 1, 5, 10, 10, 10>(base + off, ptw, t0, active);
     } else {
         int Ns = 1;
         for (int p = 0; p < d.npass; ++p) {

@@ -568,9 +568,11 @@ template <> __device__ __forceinline__ Cx<double> vfrom_real<Cx<double>>(double 
 // classes) stay below m + 64.
 __host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64; }
 
-// load(p, q, slot) returns the right-hand side of the row of coefficient q
-// (line position p: q for cosine, m - q for sine; solve-order slot);
-// store(p, x) receives the solution.  Every load happens before the first
+// load(p, q, slot, own) returns the right-hand side of the row of coefficient
+// q (line position p: q for cosine, m - q for sine; solve-order slot); own is
+// false for the repeated loads that keep the loads branch-free (a row past
+// the chunk, or an idle thread), which must not be counted twice by a load
+// that accumulates; store(p, x) receives the solution.  Every load happens before the first
 // barrier and every store after the last use of the LDS scratch.
 template <typename T, typename V, int SMAX, typename Load, typename Store>
 __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
@@ -606,7 +608,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
         const int iic = ii < cnt ? ii : 0;
         const int row = cnt > 0 ? lo + iic : 0;
         const int q = C.q0 + 2 * row;
-        r[ii] = load(lpos(q), q, cnt > 0 ? slot0 + iic * C.p : A.s * A.p);
+        r[ii] = load(lpos(q), q, cnt > 0 ? slot0 + iic * C.p : A.s * A.p, ii < cnt);
     }
     __syncthreads();   // B1: the line may now be overwritten by scratch
 
@@ -744,7 +746,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
 template <typename T, int SMAX, typename V>
 __device__ __forceinline__ void solve_partitioned(V* __restrict__ buf, unsigned char* __restrict__ scratch,
                                                   int m, int k, bool sine, bool transposed, int tid) {
-    solve_partitioned_io<T, V, SMAX>([&](int p, int, int) { return buf[p]; },
+    solve_partitioned_io<T, V, SMAX>([&](int p, int, int, bool) { return buf[p]; },
                                      [&](int p, V x) { buf[p] = x; }, scratch, m, k, sine, transposed, tid);
 }
 
@@ -803,11 +805,15 @@ __device__ __forceinline__ void scan_affine(VD& A, double& Bm, unsigned char* sc
     }
 }
 
-// buf holds the line in position order (cosine: position q); V is real or complex.
-template <typename T, int SMAX, typename V>
-__device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
-                                         bool transposed, double c0, const double* __restrict__ tab,
-                                         Cx<double>* red, int tid) {
+// load(q) returns the right-hand side of row q (position q of the cosine
+// line; q = 0 is the constraint row, read only for the transposed system);
+// store(q, x) receives the solution, q = 0 included.  Every load happens
+// before the first barrier and every store after the last use of the LDS
+// scratch.  V is real or complex.
+template <typename T, int SMAX, typename V, typename Load, typename Store>
+__device__ __forceinline__ void solve_k0_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
+                                            int m, bool transposed, double c0, const double* __restrict__ tab,
+                                            Cx<double>* red, int tid) {
     using VD = typename VTraits<V>::D;
     const int qhi = m - 1;
     const ClassInfo A = make_class<SMAX>(2, qhi);   // even q >= 2
@@ -823,14 +829,14 @@ __device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __r
     const int cnt = (inA || inB) ? min(C.s, C.nc - lo) : 0;
     const double* inv = tab + (inA ? 0 : 2 * A.nc);
     const double* cp = inv + C.nc;
-    const VD a0bar = vcast<VD>(buf[0]);
+    const VD a0bar = transposed ? vcast<VD>(load(0)) : VD{};
 
     VD r[SMAX];
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            r[ii] = vcast<VD>(buf[q]);
+            r[ii] = vcast<VD>(load(q));
             if (transposed && inA) {
                 const double om = 1.0 / (1.0 - (double)q * (double)q);
                 r[ii] = r[ii] - a0bar * om;
@@ -917,10 +923,20 @@ __device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __r
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
             const int q = C.q0 + 2 * (lo + ii);
-            buf[q] = vcast<V>(r[ii]);
+            store(q, r[ii]);
         }
     }
-    if (tid == 0) buf[0] = transposed ? V{} : vcast<V>(vfrom_real<VD>(c0) - dot);
+    if (tid == 0) store(0, transposed ? VD{} : vfrom_real<VD>(c0) - dot);
+}
+
+// In place on a line held in LDS (position order).
+template <typename T, int SMAX, typename V>
+__device__ __forceinline__ void solve_k0(V* __restrict__ buf, unsigned char* __restrict__ scratch, int m,
+                                         bool transposed, double c0, const double* __restrict__ tab,
+                                         Cx<double>* red, int tid) {
+    using VD = typename VTraits<V>::D;
+    solve_k0_io<T, SMAX, V>([&](int q) { return buf[q]; }, [&](int q, VD x) { buf[q] = vcast<V>(x); }, scratch, m,
+                            transposed, c0, tab, red, tid);
 }
 
 // Division of a column by sin(theta) in coefficient space (the paper's
@@ -1133,6 +1149,8 @@ struct ThetaMixArgs {
     const double* fint_w;
     double* fint_out;
     int k64;                   // wavenumbers below this are eliminated in float64
+    double* rnorm;             // RESID in the NORM builds: per tile (k on the complex line, 2k + part
+                               // for real parts) the sums of r^2 and F^2 over its rows
 };
 
 // k = 0 of the mixed theta pass: the bordered constraint system, always in
@@ -1144,7 +1162,8 @@ struct ThetaMixArgs {
 // On return the float32 column buff holds the solution.
 template <int SMAXD, bool RESID, bool TRANS>
 __device__ __forceinline__ void theta_mixed_k0(const ThetaMixArgs& a, Cx<double>* bufd, Cx<float>* buff,
-                                               Cx<double>* F, unsigned char* smem_raw, Cx<double>* red, int tid) {
+                                               Cx<double>* F, unsigned char* smem_raw, Cx<double>* red, int tid,
+                                               double& acc_r, double& acc_f) {
     const int m = a.m, nthr = blockDim.x;
     Cx<double> rh[kThetaHold];
     double r0 = a.c0;
@@ -1182,12 +1201,18 @@ __device__ __forceinline__ void theta_mixed_k0(const ThetaMixArgs& a, Cx<double>
                 if (TRANS && (q & 1) == 0) rhs = rhs - b0 * (1.0 / (1.0 - (double)q * (double)q));
                 rh[e] = rhs - ax;
                 if (!TRANS && (q & 1) == 0) part = part + bufd[q] * (1.0 / (1.0 - (double)q * (double)q));
+                acc_r += rh[e].x * rh[e].x + rh[e].y * rh[e].y;
+                acc_f += rhs.x * rhs.x + rhs.y * rhs.y;
             }
         }
         if (!TRANS) {
             const Cx<double> dot = block_sum(part, red);
             const Cx<double> x0 = bufd[0];
             r0 = a.c0 - (x0.x + dot.x);   // the imaginary part of the k = 0 column is zero
+            if (tid == 0) {
+                acc_r += r0 * r0;
+                acc_f += a.c0 * a.c0;
+            }
         }
         if (TRANS) x0_pin = bufd[0];
     }
@@ -1221,7 +1246,7 @@ __device__ __forceinline__ void theta_mixed_k0(const ThetaMixArgs& a, Cx<double>
 // "analysis with scaling" is the plain synthesis), transposed bands, and for
 // k = 0 the transposed bordered system (the constraint row feeds the even
 // class through -w a_0 and the q = 0 output is zero).
-template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS, bool NORM = false>
 __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, unsigned char* smem_raw,
                                                  Cx<double>* red) {
     Cx<double>* bufd = reinterpret_cast<Cx<double>*>(smem_raw);
@@ -1266,13 +1291,17 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
 
     const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
     Cx<double>* Fk = a.fco + (size_t)k * solve_slot_stride(m);
+    // NORM (correction pass only): the residual sums for the info, in a build of its own so
+    // that the plain pass carries no extra registers
+    constexpr bool want_norm = RESID && NORM;
+    double acc_r = 0.0, acc_f = 0.0;
     if (k != 0) {
         // The right-hand side of each row is formed as the solve loads it:
         // first solve, F itself (also kept, in solve order, for the
         // correction); correction, r = F - (L - k^2) X in float64 from the
         // analysed iterate X in LDS.  The solution goes straight to the
         // float32 column used by the synthesis.
-        auto load = [&](int p, int q, int slot) -> Cx<double> {
+        auto load = [&](int p, int q, int slot, bool own) -> Cx<double> {
             if (!RESID) {
                 const Cx<double> f = bufd[p];
                 Fk[slot] = f;
@@ -1283,7 +1312,12 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
             Cx<double> ax = bufd[p] * diag;
             if (q - 2 >= qlo) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
             if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
-            return Fk[slot] - ax;
+            const Cx<double> f = Fk[slot], r = f - ax;
+            if (want_norm && own) {
+                acc_r += r.x * r.x + r.y * r.y;
+                acc_f += f.x * f.x + f.y * f.y;
+            }
+            return r;
         };
         if (k < a.k64) {   // ill-conditioned low wavenumbers: float64 elimination
             solve_partitioned_io<double, Cx<double>, SMAXD>(
@@ -1291,15 +1325,22 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
                 sine, TRANS, tid);
         } else {
             solve_partitioned_io<float, Cx<float>, SMAXF>(
-                [&](int p, int q, int slot) {
-                    const Cx<double> r = load(p, q, slot);
+                [&](int p, int q, int slot, bool own) {
+                    const Cx<double> r = load(p, q, slot, own);
                     return Cx<float>{(float)r.x, (float)r.y};
                 },
                 [&](int p, Cx<float> x) { buff[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
         }
         __syncthreads();
     } else {
-        theta_mixed_k0<SMAXD, RESID, TRANS>(a, bufd, buff, Fk, smem_raw, red, tid);
+        theta_mixed_k0<SMAXD, RESID, TRANS>(a, bufd, buff, Fk, smem_raw, red, tid, acc_r, acc_f);
+    }
+    if (want_norm) {
+        const Cx<double> sm = block_sum(Cx<double>{acc_r, acc_f}, red);
+        if (tid == 0) {
+            a.rnorm[2 * k] = sm.x;
+            a.rnorm[2 * k + 1] = sm.y;
+        }
     }
     // float32 synthesis
     const float fm = (float)m;
@@ -1324,13 +1365,13 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
     }
 }
 
-template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS, bool NORM = false>
 __global__ void __launch_bounds__(1024) k_theta_mixed(ThetaMixArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Cx<double> red[16];
     const int k = theta_k_of_block(a.k8);
     if (k > a.N) return;
-    theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS>(a, k, smem_raw, red);
+    theta_mixed_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS, NORM>(a, k, smem_raw, red);
 }
 
 }  // namespace sp

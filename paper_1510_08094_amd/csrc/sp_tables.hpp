@@ -23,6 +23,9 @@ constexpr int kBatchSmallRadix = 16;
 constexpr int kBatchRealThreads = 128;
 constexpr int kBatchSmaxR = 17;    // chunk rows per thread in those tiles: the shortest that lets m = 2048 fit
 constexpr int kBatchWaveThreads = 64;
+constexpr int kBatchScal = 16;          // device scalars per problem: integral of f, correction norms
+constexpr int kBatchMaxLaunches = 64;   // stage launches in one batch graph (one work-list counter each)
+constexpr int kBatchMaxRefine = 4;      // corrections in a mixed batch
 
 template <typename T>
 struct KernelSet {
@@ -38,6 +41,8 @@ struct MixedSet {
     void (*theta_resid[2])(ThetaMixArgs);
     void (*theta_first_t[2])(ThetaMixArgs);   // transposed systems (adjoint)
     void (*theta_resid_t[2])(ThetaMixArgs);
+    void (*theta_resid_norm[2])(ThetaMixArgs);     // correction pass that also sums the residual norms
+    void (*theta_resid_t_norm[2])(ThetaMixArgs);
     void (*mix)(MixLambdaArgs);
     void (*update)(MixLambdaArgs);
 };

@@ -152,6 +152,9 @@ __device__ __forceinline__ double load_part(T* y, const Cx<TS>* __restrict__ spe
 template <typename T, typename TS>
 __device__ __forceinline__ void store_part(const T* y, Cx<TS>* __restrict__ spec, int part, int k, int m, int N,
                                            int lay, bool sine, T scale, int tid, int nthr) {
+    // the index arithmetic is redone here rather than kept from the load (it
+    // would stay live in registers, or spill, across the whole pass)
+    asm volatile("" : "+v"(tid));
     TS* sp = reinterpret_cast<TS*>(spec) + part + 2 * spec_at(tid, k, N, lay);
     const size_t dj = (size_t)2 * (((size_t)(nthr >> lay) * (N + 1)) << lay);
     const bool odd = (tid & 1) != 0;
@@ -220,76 +223,52 @@ __global__ void __launch_bounds__(512, 4) k_theta_real(ThetaArgs<T> a) {
 // ---------------------------------------------------------------- mixed precision pass
 // k = 0 of the mixed real pass (see theta_mixed_k0 for the complex line): the
 // bordered system in float64, F kept in position order; on return the
-// float32 line yf holds the solution.
+// float32 line yf holds the solution.  The right-hand side of each row is
+// formed as the solve loads it (F on the first pass; on a correction pass
+// the residual of the current iterate yd, whose constraint row needs the
+// block sum of its even coefficients first), and the solution goes straight
+// to the float32 line: no line values are held in registers across the solve.
 template <int SMAXD, bool RESID, bool TRANS>
 __device__ __forceinline__ void theta_mixed_real_k0(const ThetaMixArgs& a, int part, double* yd, float* yf,
                                                     double* F, unsigned char* smem_raw, Cx<double>* red,
-                                                    int tid) {
+                                                    int tid, double& acc_r, double& acc_f) {
     const int m = a.m, nthr = blockDim.x;
-    double rh[kRealLoadHold];
-    double r0 = part == 0 ? a.c0 : 0.0;
-    double x0_pin = 0.0;
     const int qhi = m - 1;
-    if (!RESID) {
-#pragma unroll
-        for (int e = 0; e < kRealLoadHold; ++e) {
-            const int p = tid + e * nthr;
-            if (p < m) {
-                rh[e] = yd[p];
-                F[p] = rh[e];
-            }
-        }
-    } else {
+    double r0 = part == 0 ? a.c0 : 0.0;
+    if (RESID && !TRANS) {
         double dotp = 0.0;
-        const double b0 = TRANS ? F[0] : 0.0;
-#pragma unroll
-        for (int e = 0; e < kRealLoadHold; ++e) {
-            const int q = tid + e * nthr;
-            if (q < m) {
-                if (q == 0) {
-                    rh[e] = 0.0;
-                    continue;
-                }
-                const int lo_q = (TRANS && (q & 1) == 0) ? 2 : 0;
-                double sub, diag, sup;
-                band<double>(q, 0, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
-                double ax = yd[q] * diag;
-                if (q - 2 >= lo_q) ax += yd[q - 2] * sub;
-                if (q + 2 <= qhi) ax += yd[q + 2] * sup;
-                double rhs = F[q];
-                if (TRANS && (q & 1) == 0) rhs -= b0 * (1.0 / (1.0 - (double)q * (double)q));
-                rh[e] = rhs - ax;
-                if (!TRANS && (q & 1) == 0) dotp += yd[q] * (1.0 / (1.0 - (double)q * (double)q));
-            }
+        for (int q = 2 * tid + 2; q <= qhi; q += 2 * nthr) dotp += yd[q] * (1.0 / (1.0 - (double)q * (double)q));
+        const double c = r0;
+        r0 = r0 - (yd[0] + block_sum(dotp, red));
+        if (tid == 0) {
+            acc_r += r0 * r0;
+            acc_f += c * c;
         }
-        if (!TRANS) {
-            const double dot = block_sum(dotp, red);
-            r0 = r0 - (yd[0] + dot);
+    }
+    const double x0_pin = (RESID && TRANS) ? yd[0] : 0.0;
+    const double b0 = (RESID && TRANS) ? F[0] : 0.0;
+    if (!RESID && tid == 0) F[0] = yd[0];
+    auto load = [&](int q) -> double {
+        if (!RESID) {
+            const double f = yd[q];
+            if (q != 0) F[q] = f;
+            return f;
         }
-        if (TRANS) x0_pin = yd[0];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kRealLoadHold; ++e) {
-        const int p = tid + e * nthr;
-        if (p < m) yd[p] = rh[e];
-    }
-    __syncthreads();
-    solve_k0<double, SMAXD>(yd, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
-    __syncthreads();
-    if (TRANS && RESID && tid == 0) yd[0] = -x0_pin;
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kRealLoadHold; ++e) {
-        const int p = tid + e * nthr;
-        if (p < m) rh[e] = yd[p];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kRealLoadHold; ++e) {
-        const int p = tid + e * nthr;
-        if (p < m) yf[p] = (float)rh[e];
-    }
+        if (q == 0) return 0.0;
+        const int lo_q = (TRANS && (q & 1) == 0) ? 2 : 0;
+        double sub, diag, sup;
+        band<double>(q, 0, q - 2 < lo_q, q + 2 > qhi, TRANS, sub, diag, sup);
+        double ax = yd[q] * diag;
+        if (q - 2 >= lo_q) ax += yd[q - 2] * sub;
+        if (q + 2 <= qhi) ax += yd[q + 2] * sup;
+        double rhs = F[q];
+        if (TRANS && (q & 1) == 0) rhs -= b0 * (1.0 / (1.0 - (double)q * (double)q));
+        acc_r += (rhs - ax) * (rhs - ax);
+        acc_f += rhs * rhs;
+        return rhs - ax;
+    };
+    auto store = [&](int q, double x) { yf[q] = (float)((TRANS && RESID && q == 0) ? -x0_pin : x); };
+    solve_k0_io<double, SMAXD, double>(load, store, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
     __syncthreads();
 }
 
@@ -297,7 +276,7 @@ __device__ __forceinline__ void theta_mixed_real_k0(const ThetaMixArgs& a, int p
 // of the part (F on the first pass; the current iterate on a correction
 // pass), the right-hand side formed as the solve loads it, float32 (low k:
 // float64) elimination, float32 synthesis written to that part of `out`.
-template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS, bool NORM = false>
 __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int k, int part,
                                                       unsigned char* smem_raw, Cx<double>* red) {
     double* yd = reinterpret_cast<double*>(smem_raw);
@@ -321,8 +300,12 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
 
     const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
     double* Fk = reinterpret_cast<double*>(a.fco) + (size_t)(2 * k + part) * solve_slot_stride(m);
+    // NORM (correction pass only): the residual sums for the info, in a build of its own so
+    // that the plain pass carries no extra registers
+    constexpr bool want_norm = RESID && NORM;
+    double acc_r = 0.0, acc_f = 0.0;
     if (k != 0) {
-        auto load = [&](int p, int q, int slot) -> double {
+        auto load = [&](int p, int q, int slot, bool own) -> double {
             if (!RESID) {
                 const double f = yd[p];
                 Fk[slot] = f;
@@ -333,19 +316,31 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
             double ax = yd[p] * diag;
             if (q - 2 >= qlo) ax += yd[sine ? p + 2 : p - 2] * sub;
             if (q + 2 <= qhi) ax += yd[sine ? p - 2 : p + 2] * sup;
-            return Fk[slot] - ax;
+            const double f = Fk[slot], r = f - ax;
+            if (want_norm && own) {
+                acc_r += r * r;
+                acc_f += f * f;
+            }
+            return r;
         };
         if (k < a.k64) {
             solve_partitioned_io<double, double, SMAXD>(
                 load, [&](int p, double x) { yf[p] = (float)x; }, smem_raw, m, k, sine, TRANS, tid);
         } else {
             solve_partitioned_io<float, float, SMAXF>(
-                [&](int p, int q, int slot) { return (float)load(p, q, slot); },
+                [&](int p, int q, int slot, bool own) { return (float)load(p, q, slot, own); },
                 [&](int p, float x) { yf[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
         }
         __syncthreads();
     } else {
-        theta_mixed_real_k0<SMAXD, RESID, TRANS>(a, part, yd, yf, Fk, smem_raw, red, tid);
+        theta_mixed_real_k0<SMAXD, RESID, TRANS>(a, part, yd, yf, Fk, smem_raw, red, tid, acc_r, acc_f);
+    }
+    if (want_norm) {
+        const Cx<double> sm = block_sum(Cx<double>{acc_r, acc_f}, red);
+        if (tid == 0) {
+            a.rnorm[2 * (2 * k + part)] = sm.x;
+            a.rnorm[2 * (2 * k + part) + 1] = sm.y;
+        }
     }
     const float fm = (float)m;
     rdct_split_inverse<float>(yf, a.eq32, a.ws32, m, TRANS ? 1.0f : fm, TRANS ? 1.0f : 0.5f * fm, tid, nthr);
@@ -353,14 +348,14 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
     store_part<float, float>(yf, a.out, part, k, m, N, a.lay_out_log2, sine, 1.0f / fm, tid, nthr);
 }
 
-template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS>
+template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS, bool NORM = false>
 __global__ void __launch_bounds__(512, 4) k_theta_mixed_real(ThetaMixArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Cx<double> red[8];
     int k, part;
     real_theta_tile(a.k8, &k, &part);
     if (k > a.N) return;
-    theta_mixed_real_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS>(a, k, part, smem_raw, red);
+    theta_mixed_real_body<EPT, RMAX, SMAXF, SMAXD, RESID, TRANS, NORM>(a, k, part, smem_raw, red);
 }
 
 }  // namespace sp

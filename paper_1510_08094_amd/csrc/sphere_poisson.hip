@@ -25,6 +25,7 @@
 #include "sp_calculus.hpp"
 #include "sp_lowrank.hpp"
 #include "sp_tables.hpp"
+#include "sp_stream.hpp"
 
 using sp::Cx;
 using sp::FftDesc;
@@ -39,6 +40,8 @@ using sp::kBatchSmallRadix;
 using sp::kBatchRealThreads;
 using sp::kBatchSmaxR;
 using sp::kBatchWaveThreads;
+using sp::kBatchScal;
+using sp::kBatchMaxLaunches;
 using sp::KernelSet;
 using sp::MixedSet;
 using sp::BatchKernels;
@@ -87,6 +90,12 @@ void cis_neg(long long t, long long N, double* re, double* im) {
 }
 
 // ------------------------------------------------------------ FFT planning
+// The compiled-in transform of length 5000 (radices 5, 10, 10, 10): its
+// radix-10 passes exist only in that fixed build.
+bool is_fixed5000(const std::vector<int>& rad, int L) {
+    return L == 5000 && rad == std::vector<int>(std::begin(sp::kFixed5000Radices), std::end(sp::kFixed5000Radices));
+}
+
 bool factorize(int L, std::vector<int>& radices) {
     radices.clear();
     if (L < 1) return false;
@@ -111,6 +120,16 @@ bool factorize(int L, std::vector<int>& radices) {
 
 int bpt(int R) { return std::max(1, kEPT / R); }
 
+// Default radix order of a length: the fixed transform where one is compiled
+// in, else factorize().
+bool default_radices(int L, std::vector<int>& radices) {
+    if (L == 5000) {
+        radices.assign(std::begin(sp::kFixed5000Radices), std::end(sp::kFixed5000Radices));
+        return true;
+    }
+    return factorize(L, radices);
+}
+
 int fft_threads(const std::vector<int>& rad, int L) {
     int t = 1;
     for (int R : rad) t = std::max(t, ((L / R) + bpt(R) - 1) / bpt(R));
@@ -125,7 +144,7 @@ FftDesc make_desc(const std::vector<int>& rad, int L, std::vector<Cx<double>>* t
     d.N = L;
     d.npass = (int)rad.size();
     // compiled-in fixed transforms (used when the thread count also matches)
-    if (L == 5000 && rad == std::vector<int>{5, 5, 5, 5, 8}) d.fixed = sp::kFixed5000;
+    if (is_fixed5000(rad, L)) d.fixed = sp::kFixed5000;
     table->clear();
     long long Ns = 1;
     for (size_t i = 0; i < rad.size(); ++i) {
@@ -188,6 +207,29 @@ struct Tables {
 
 }  // namespace
 
+// A batch plan (sphere_poisson_batch_plan): every problem's workspace and
+// tables in one allocation, the work lists, and the captured graph.
+struct sp_batch_s {
+    int count = 0, precision = 0, device = 0, max_refine = 0;
+    double tol = 0.0;
+    std::vector<int> n, m;
+    void* block = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;   // recorded after every launch: destroy waits for it
+    bool launched = false;
+    double* scal = nullptr;      // [count][kBatchScal]: [0] integral of f, then per correction sums d^2, u^2
+    ~sp_batch_s() {
+        if (done && launched) (void)hipEventSynchronize(done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (done) (void)hipEventDestroy(done);
+        if (block) (void)hipFree(block);
+    }
+};
+
 // ------------------------------------------------------------ plan
 struct sp_plan_s {
     sp_desc desc{};
@@ -223,13 +265,17 @@ struct sp_plan_s {
     double* sin2 = nullptr;
     double* k0tab = nullptr;
     double* fint_w = nullptr;
-    double* scal = nullptr;   // device scalars: [0] = integral of f, [1..2] = sum d^2, sum u^2
+    // device scalars: [0] integral of f; [1..2] sums d^2, u^2 of the last correction; [3..4] sums r^2,
+    // F^2 of the last correction pass's residual; [5..6] sums d^2, u^2 of the correction before the last
+    double* scal = nullptr;
     size_t spec_elems = 0;
+    int last_status = SP_OK, last_iters = 0;   // of the last solve or adjoint (sphere_poisson_get_info)
     // MIXED workspace
     Cx<double>* specB = nullptr;   // float64: theta output; mixed: spectrum of the current iterate
     Cx<float>* spec0 = nullptr;    // float32 spectrum of the first iterate
     Cx<float>* specd = nullptr;    // float32 spectrum of the correction
     double* partial = nullptr;     // per lambda block: sum d^2, sum u^2
+    double* rnorm = nullptr;       // per theta tile: sums r^2, F^2 of the correction pass
     Cx<double>* fco = nullptr;     // theta coefficients F of sin^2 f per wavenumber (solve order)
     // profiling: event pairs around launches
     std::vector<hipEvent_t> ev;
@@ -248,6 +294,15 @@ bool plan_ok(sp_plan p) {
     return g_plans.count(p) != 0;
 }
 
+std::mutex g_batches_mu;
+std::set<sp_batch> g_batches;   // live batch plans (same rule as g_plans)
+
+bool batch_ok(sp_batch b) {
+    if (!b) return false;
+    std::lock_guard<std::mutex> g(g_batches_mu);
+    return g_batches.count(b) != 0;
+}
+
 void plan_register(sp_plan p) {
     std::lock_guard<std::mutex> g(g_plans_mu);
     g_plans.insert(p);
@@ -262,7 +317,7 @@ int validate_desc(const sp_desc* d) {
     if (!d) return SP_ERR_INVALID_ARG;
     if (d->n_lambda < 4 || (d->n_lambda & 1) || d->m_theta < 4) return SP_ERR_INVALID_ARG;
     if (d->precision != SP_FP64 && d->precision != SP_MIXED) return SP_ERR_INVALID_ARG;
-    if (d->max_refine < 0 || (d->flags & ~(SP_SYNC_INFO | SP_AUTOTUNE))) return SP_ERR_INVALID_ARG;
+    if (d->max_refine < 0 || (d->flags & ~(SP_SYNC_INFO | SP_AUTOTUNE | SP_INFO))) return SP_ERR_INVALID_ARG;
     if (d->n_lambda > (1 << 20) || d->m_theta > (1 << 20)) return SP_ERR_UNSUPPORTED_SIZE;
     std::vector<int> r;
     if (!factorize(d->n_lambda / 2, r) || !factorize(d->m_theta, r)) return SP_ERR_UNSUPPORTED_SIZE;
@@ -273,7 +328,7 @@ struct Layout {
     size_t off_spec, off_tw64n, off_tw64m, off_eq64, off_tw32n, off_tw32m, off_eq32, off_p64n, off_p32n;
     size_t off_ws64, off_ws32;
     size_t off_sin2, off_k0, off_fint, off_scal, total;
-    size_t off_specB, off_spec0, off_specd, off_partial, off_fco;
+    size_t off_specB, off_spec0, off_specd, off_partial, off_fco, off_rnorm;
     size_t off_grad, off_intw, off_intpart;
     size_t spec_elems;
 };
@@ -313,6 +368,7 @@ Layout layout_for(int n, int m, int rw, int rl, bool mixed) {
         L.off_spec0 = take(L.spec_elems * sizeof(Cx<float>));
         L.off_specd = take(L.spec_elems * sizeof(Cx<float>));
         L.off_partial = take(2 * nblk * sizeof(double));
+        L.off_rnorm = take(4 * (N + 1) * sizeof(double));
         L.off_fco = take((N + 1) * (size_t)sp::solve_slot_stride(m) * sizeof(Cx<double>));
     }
     L.total = off;
@@ -434,7 +490,7 @@ void host_theta_tables(int m, std::vector<Cx<double>>& eq, std::vector<double>& 
 extern "C" size_t sphere_poisson_workspace_bytes(const sp_desc* d) {
     if (validate_desc(d) != SP_OK) return 0;
     std::vector<int> rl;
-    factorize(d->n_lambda / 2, rl);
+    default_radices(d->n_lambda / 2, rl);
     int rwl = 0, nt = 0;
     size_t lds = 0;
     if (!lambda_schedule(d->n_lambda / 2, d->m_theta, rl, 160 * 1024, &rwl, &nt, &lds)) return 0;
@@ -475,7 +531,7 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         const int M = m / 2, ptotR = solve_threads(m, kSmaxR);
         std::vector<int> r = sc.theta;
         if (!valid_radices(r, M)) r.clear();
-        if (r.empty() && !factorize(M, r)) r.clear();
+        if (r.empty() && !default_radices(M, r)) r.clear();
         if (!r.empty()) {
             const int fthr = fft_threads(r, M);
             const int thr = round_up(std::max(std::max(fthr, ptotR), sp::real_theta_min_threads(m)), 64);
@@ -493,8 +549,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     const int Lt = p->theta_real ? m / 2 : m;
     if (!valid_radices(rl, N)) rl.clear();
     if (!valid_radices(rt, Lt)) rt.clear();
-    if (rl.empty()) factorize(N, rl);
-    if (rt.empty()) factorize(Lt, rt);
+    if (rl.empty()) default_radices(N, rl);
+    if (rt.empty()) default_radices(Lt, rt);
     std::vector<Cx<double>> ptab_n, ptab_m;
     p->fft_lam = make_desc(rl, N, &ptab_n);
     p->fft_theta = make_desc(rt, Lt, &ptab_m);
@@ -543,7 +599,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     set_lds_attr(p->kf, p->lam_lds, p->theta_lds64);
     for (int v = 0; v < 2; ++v)
         for (const void* fn : {(const void*)p->km.theta_first[v], (const void*)p->km.theta_resid[v],
-                               (const void*)p->km.theta_first_t[v], (const void*)p->km.theta_resid_t[v]})
+                               (const void*)p->km.theta_first_t[v], (const void*)p->km.theta_resid_t[v],
+                               (const void*)p->km.theta_resid_norm[v], (const void*)p->km.theta_resid_t_norm[v]})
             if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
@@ -600,6 +657,7 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         p->spec0 = (Cx<float>*)(b + L.off_spec0);
         p->specd = (Cx<float>*)(b + L.off_specd);
         p->partial = (double*)(b + L.off_partial);
+        p->rnorm = (double*)(b + L.off_rnorm);
         p->fco = (Cx<double>*)(b + L.off_fco);
     }
 
@@ -737,6 +795,7 @@ std::string key_lam(int n) { return "gfx950 lam " + std::to_string(n); }
 std::string key_theta(int m, int prec) { return "gfx950 theta " + std::to_string(m) + " " + std::to_string(prec); }
 
 bool valid_radices(const std::vector<int>& r, int L) {
+    if (is_fixed5000(r, L)) return true;
     long long prod = 1;
     for (int x : r) {
         static const int ok[] = {2, 3, 4, 5, 7, 8, 11, 13, 16, 17, 19, 23, 29, 31};
@@ -751,6 +810,7 @@ bool valid_radices(const std::vector<int>& r, int L) {
 // a few orders.
 std::vector<std::vector<int>> radix_candidates(int L) {
     std::vector<std::vector<int>> out;
+    if (L == 5000) out.push_back(std::vector<int>(std::begin(sp::kFixed5000Radices), std::end(sp::kFixed5000Radices)));
     int e = 0, odd = L;
     while (odd % 2 == 0) { odd /= 2; ++e; }
     std::vector<int> primes;
@@ -1033,7 +1093,6 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
              bool adjoint_weights, bool want_fint, hipStream_t s) {
     const int n = p->n, m = p->m, N = p->N;
     const int rw = 1 << p->rw_log2;
-    const int nblk = (m + rw - 1) / rw;
     sp::LambdaArgs<double> la{};
     la.x = in;
     la.y = out;
@@ -1086,23 +1145,45 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     return SP_OK;
 }
 
-int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status, int iters) {
-    if (!(p->desc.flags & SP_SYNC_INFO)) return status;
+// The info of a solve from the device scalars (after a synchronisation);
+// `norms`: the plan collected them (SP_SYNC_INFO or SP_INFO), else they read -1.
+int read_info(sp_plan p, hipStream_t s, sp_info* info, int status, int iters, bool norms) {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    double sc[3] = {0.0, 0.0, 0.0};
+    double sc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     e = hipMemcpy(sc, p->scal, sizeof(sc), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy info");
-    double rel = 0.0;
-    if (iters > 0) rel = sc[2] > 0.0 ? std::sqrt(sc[1] / sc[2]) : 0.0;
-    if (iters > 0 && p->desc.tol > 0.0 && !(rel <= p->desc.tol)) status = SP_ERR_NOT_CONVERGED;
-    if (p->desc.precision == SP_MIXED && iters == 0 && p->desc.tol > 0.0) status = SP_ERR_NOT_CONVERGED;
+    double rel = 0.0, res = 0.0, est = 0.0;
+    if (iters > 0 && norms) {
+        rel = sc[2] > 0.0 ? std::sqrt(sc[1] / sc[2]) : 0.0;
+        res = sc[4] > 0.0 ? std::sqrt(sc[3] / sc[4]) : 0.0;
+        // contraction: the ratio of the last two corrections, or with one
+        // correction its own relative size (the float32 solve's relative error)
+        const double prev = (iters >= 2 && sc[6] > 0.0) ? std::sqrt(sc[5] / sc[6]) : 0.0;
+        const double rho = iters >= 2 ? (prev > 0.0 ? rel / prev : 0.0) : rel;
+        est = rel * rho;
+    } else if (!norms && p->desc.precision == SP_MIXED) {
+        rel = res = est = -1.0;
+    }
+    if (norms && iters > 0 && p->desc.tol > 0.0 && !(rel <= p->desc.tol)) status = SP_ERR_NOT_CONVERGED;
+    if (norms && p->desc.precision == SP_MIXED && iters == 0 && p->desc.tol > 0.0) status = SP_ERR_NOT_CONVERGED;
     if (info) {
         info->iters = iters;
         info->rel_correction = rel;
         info->f_integral = sc[0];
         info->status = status;
+        info->rel_residual = res;
+        info->est_rel_err = est;
     }
+    return status;
+}
+
+int finish_info(sp_plan p, hipStream_t s, sp_info* info, int status, int iters) {
+    p->last_status = status;
+    p->last_iters = iters;
+    if (!(p->desc.flags & SP_SYNC_INFO)) return status;
+    status = read_info(p, s, info, status, iters, true);
+    p->last_status = status;
     return status;
 }
 
@@ -1112,10 +1193,11 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     const int n = p->n, m = p->m, N = p->N;
     const int rw = 1 << p->rw_log2;
     const int nblk = (m + rw - 1) / rw;
-    const bool want = (p->desc.flags & SP_SYNC_INFO) != 0;
+    const bool want = (p->desc.flags & (SP_SYNC_INFO | SP_INFO)) != 0;
     const dim3 lam_grid(p->lam_grid), lam_block(round_up(rw * p->lam_threads, 64));
     const dim3 th_grid(p->theta_grid), th_block(p->theta_threads);
     const int tv = p->theta_real ? 1 : 0;
+    const int ntiles = p->theta_real ? 2 * (N + 1) : N + 1;   // theta tiles (residual-norm partials)
     // 1. float64 lambda transform of sin^2 f -> spec64
     sp::LambdaArgs<double> la{};
     // forward: sin^2 f with weight 1/n; adjoint: the transpose of the inverse real DFT
@@ -1142,6 +1224,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     ta.nthr_fft = p->theta_fft_threads; ta.k8 = p->k8; ta.c0 = c0; ta.k0tab = p->k0tab;
     ta.fint_w = p->fint_w; ta.fint_out = p->scal;
     ta.k64 = p->desc.low_k_fp64 < 0 ? std::max(16, m / 64) : std::max(1, p->desc.low_k_fp64);
+    ta.rnorm = nullptr;
     {
         ProfScope ps(p, SP_KERNEL_THETA, s);
         hipLaunchKernelGGL(adjoint ? p->km.theta_first_t[tv] : p->km.theta_first[tv], th_grid, th_block, p->theta_lds64,
@@ -1191,10 +1274,14 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
                 ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
                 hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
             }
+            // the last correction pass also sums the residual of its iterate (info builds)
+            const bool norm = want && it == R;
+            ta.rnorm = norm ? p->rnorm : nullptr;
             {
                 ProfScope ps(p, SP_KERNEL_THETA_RESID, s);
-                hipLaunchKernelGGL(adjoint ? p->km.theta_resid_t[tv] : p->km.theta_resid[tv], th_grid, th_block,
-                                   p->theta_lds64, s, ta);
+                auto* fn = adjoint ? (norm ? p->km.theta_resid_t_norm[tv] : p->km.theta_resid_t[tv])
+                                   : (norm ? p->km.theta_resid_norm[tv] : p->km.theta_resid[tv]);
+                hipLaunchKernelGGL(fn, th_grid, th_block, p->theta_lds64, s, ta);
             }
             ma.accumulate = it > 1 ? 1 : 0;
             {
@@ -1202,11 +1289,17 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
                 // float32 correction lines only: half the LDS of the other lambda passes
                 hipLaunchKernelGGL(p->km.update, lam_grid, lam_block, p->lam_lds / 2, s, ma);
             }
+            // correction norms of the last two corrections: [1..2] last, [5..6] the one before
+            if (want && it >= R - 1) {
+                ProfScope ps(p, SP_KERNEL_REDUCE, s);
+                hipLaunchKernelGGL(sp::k_reduce_partials, dim3(1), dim3(256), 0, s, (const double*)p->partial, nblk,
+                                   p->scal + (it == R ? 1 : 5));
+            }
         }
         if (want) {
             ProfScope ps(p, SP_KERNEL_REDUCE, s);
-            hipLaunchKernelGGL(sp::k_reduce_partials, dim3(1), dim3(256), 0, s, (const double*)p->partial, nblk,
-                               p->scal + 1);
+            hipLaunchKernelGGL(sp::k_reduce_partials, dim3(1), dim3(256), 0, s, (const double*)p->rnorm, ntiles,
+                               p->scal + 3);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1345,7 +1438,9 @@ extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* 
     if (overlap(g, fbar, bytes)) return SP_ERR_ALIAS;
     hipStream_t s = (hipStream_t)hip_stream;
     if (p->desc.precision == SP_MIXED) {
-        const int R = std::min(p->desc.max_refine, 1);
+        // the adjoint refinement supports one correction (see run_mixed_adjoint)
+        if (p->desc.max_refine > 1) return SP_ERR_INVALID_ARG;
+        const int R = p->desc.max_refine;
         int st = run_mixed_adjoint(p, g, fbar, R, s);
         if (st != SP_OK) return st;
         return finish_info(p, s, info, SP_OK, R);
@@ -1353,6 +1448,15 @@ extern "C" int sphere_poisson_solve_adjoint(sp_plan p, const double* g, double* 
     int st = run_fp64(p, g, fbar, sp::kSolveTransposed, 0.0, false, true, false, s);
     if (st != SP_OK) return st;
     return finish_info(p, s, info, SP_OK, 0);
+}
+
+extern "C" int sphere_poisson_get_info(sp_plan p, void* hip_stream, sp_info* info) {
+    if (!plan_ok(p)) return SP_ERR_BAD_PLAN;
+    if (!info) return SP_ERR_INVALID_ARG;
+    const bool norms = (p->desc.flags & (SP_SYNC_INFO | SP_INFO)) != 0;
+    const int st = read_info(p, (hipStream_t)hip_stream, info, p->last_status, p->last_iters, norms);
+    // a HIP failure is the call's own error; otherwise the last solve's status
+    return st == SP_ERR_HIP ? st : SP_OK;
 }
 
 extern "C" int sphere_poisson_transform_roundtrip(sp_plan p, const double* f, double* out, void* hip_stream) {
@@ -1545,26 +1649,6 @@ struct SizeTables {              // tables shared by every problem with the same
     size_t offws64 = 0, offws32 = 0;   // theta: real-part split twiddles
 };
 
-struct BatchPlan {
-    int count = 0, precision = 0, device = 0;
-    std::vector<int> n, m;
-    std::vector<const double*> f;
-    std::vector<double*> u;
-    void* block = nullptr;
-    hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    double* scal = nullptr;      // [count][4]
-    ~BatchPlan() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (cap) (void)hipStreamDestroy(cap);
-        if (block) (void)hipFree(block);
-    }
-};
-
-std::mutex g_batch_mu;
-BatchPlan* g_batch = nullptr;   // the plan of the last size/pointer list (rebuilt when it changes)
 
 // Builds of every stage (a problem's class per stage):
 //   0: radices up to 16, 256 threads, 128 registers (168 for the complex
@@ -1641,7 +1725,7 @@ void host_theta_tables(int m, std::vector<Cx<double>>& eq, std::vector<double>& 
                        std::vector<double>& fint);
 
 int build_batch(int count, const int* n, const int* m, const double* const* f, double* const* u, int precision,
-                BatchPlan** out) {
+                int R, double tol, bool tune, sp_batch_s** out) {
     int dev = 0;
     size_t lds_limit = 0;
     int st = query_device(&dev, &lds_limit);
@@ -1651,7 +1735,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     const bool mixed = precision == SP_MIXED;
     // radix orders per distinct n and m: the autotuner cache, measured first when requested
     const char* env = std::getenv("SPHERE_POISSON_AUTOTUNE");
-    if (env && *env == '1') {
+    if (tune || (env && *env == '1')) {
         std::map<int, int> seen_n, seen_m;
         for (int r = 0; r < count; ++r) {
             if (seen_n.count(n[r]) && seen_m.count(m[r])) continue;
@@ -1680,15 +1764,15 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         treal[r] = re;
     }
 
-    BatchPlan* bp = new (std::nothrow) BatchPlan();
+    sp_batch_s* bp = new (std::nothrow) sp_batch_s();
     if (!bp) return SP_ERR_OOM;
     bp->count = count;
     bp->precision = precision;
     bp->device = dev;
+    bp->max_refine = mixed ? R : 0;
+    bp->tol = tol;
     bp->n.assign(n, n + count);
     bp->m.assign(m, m + count);
-    bp->f.assign(f, f + count);
-    bp->u.assign(u, u + count);
 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
@@ -1790,13 +1874,16 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     const size_t o_thf = mixed ? take(count * sizeof(sp::ThetaMixArgs)) : 0;
     const size_t o_thr = mixed ? take(count * sizeof(sp::ThetaMixArgs)) : 0;
     const size_t o_mix = mixed ? take(count * sizeof(sp::MixLambdaArgs)) : 0;
+    // corrections after the first: float64 transform of the iterate, then an accumulating update
+    const size_t o_lfwd2 = (mixed && R > 1) ? take(count * sizeof(sp::LambdaArgs<double>)) : 0;
+    const size_t o_mix2 = (mixed && R > 1) ? take(count * sizeof(sp::MixLambdaArgs)) : 0;
     size_t o_lam_items[kBatchClasses], o_th_items[kBatchClasses];
     for (int c = 0; c < kBatchClasses; ++c) {
         o_lam_items[c] = take(lam_items[c].size() * sizeof(int2));
         o_th_items[c] = take(th_items[c].size() * sizeof(int2));
     }
-    const size_t o_ctr = take(sp::kBStages * kBatchClasses * sizeof(int));
-    const size_t o_scal = take(4 * (size_t)count * sizeof(double));
+    const size_t o_ctr = take(kBatchMaxLaunches * sizeof(int));
+    const size_t o_scal = take(kBatchScal * (size_t)count * sizeof(double));
     const size_t o_nblk = take(count * sizeof(int));
 
     hipError_t e = hipMalloc(&bp->block, off);
@@ -1837,7 +1924,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         d.sin2 = (const double*)(B + T.offsin2);
         d.k0tab = (const double*)(B + T.offk0);
         d.fint_w = (const double*)(B + T.offfint);
-        d.scal = bp->scal + 4 * r;
+        d.scal = bp->scal + kBatchScal * r;
     }
     auto to32 = [](const std::vector<Cx<double>>& v) {
         std::vector<Cx<float>> o(v.size());
@@ -1878,7 +1965,8 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         std::vector<sp::LambdaArgs<double>> lf(count), li(count);
         std::vector<sp::ThetaArgs<double>> t64(count);
         std::vector<sp::ThetaMixArgs> tf(count), tr(count);
-        std::vector<sp::MixLambdaArgs> mx(count);
+        std::vector<sp::MixLambdaArgs> mx(count), mx2(count);
+        std::vector<sp::LambdaArgs<double>> lf2(count);
         for (int r = 0; r < count; ++r) {
             lf[r] = sp::batch_lambda_args(descs[r], true);
             li[r] = sp::batch_lambda_args(descs[r], false);
@@ -1886,12 +1974,24 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             tf[r] = sp::batch_theta_mix_args(descs[r], false);
             tr[r] = sp::batch_theta_mix_args(descs[r], true);
             mx[r] = sp::batch_mix_args(descs[r]);
+            // later corrections: the float64 spectrum of the current iterate u (no sin^2) into specB,
+            // and an update that adds the correction to u
+            lf2[r] = lf[r];
+            lf2[r].x = descs[r].u;
+            lf2[r].rowscale = nullptr;
+            lf2[r].spec = descs[r].specB;
+            mx2[r] = mx[r];
+            mx2[r].accumulate = 1;
         }
         stage(o_lfwd, lf.data(), count * sizeof(lf[0]));
         if (mixed) {
             stage(o_thf, tf.data(), count * sizeof(tf[0]));
             stage(o_thr, tr.data(), count * sizeof(tr[0]));
             stage(o_mix, mx.data(), count * sizeof(mx[0]));
+            if (R > 1) {
+                stage(o_lfwd2, lf2.data(), count * sizeof(lf2[0]));
+                stage(o_mix2, mx2.data(), count * sizeof(mx2[0]));
+            }
         } else {
             stage(o_linv, li.data(), count * sizeof(li[0]));
             stage(o_th64, t64.data(), count * sizeof(t64[0]));
@@ -1907,17 +2007,30 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         if (e != hipSuccess) { delete bp; return hip_fail(e, "batch upload"); }
     }
 
-    // graph: counter reset, the stage kernels, per-problem norms
+    // graph: counter reset, the stage kernels (the correction stages R times), per-problem norms
     BatchKernels K = batch_kernels();
-    std::vector<int> stages = mixed ? std::vector<int>{sp::kBLamFwd, sp::kBThetaFirst, sp::kBLamMix,
-                                                       sp::kBThetaResid, sp::kBLamUpd}
-                                    : std::vector<int>{sp::kBLamFwd, sp::kBTheta64, sp::kBLamInv};
+    struct Step { int stg; size_t args; int norm_slot; };   // norm_slot >= 0: per-problem norms after it
+    std::vector<Step> steps;
+    if (mixed) {
+        steps = {{sp::kBLamFwd, o_lfwd, -1}, {sp::kBThetaFirst, o_thf, -1}, {sp::kBLamMix, o_mix, -1},
+                 {sp::kBThetaResid, o_thr, -1}, {sp::kBLamUpd, o_mix, 1}};
+        for (int it = 2; it <= R; ++it) {
+            steps.push_back({sp::kBLamFwd, o_lfwd2, -1});
+            steps.push_back({sp::kBThetaResid, o_thr, -1});
+            steps.push_back({sp::kBLamUpd, o_mix2, 1 + 2 * (it - 1)});
+        }
+    } else {
+        steps = {{sp::kBLamFwd, o_lfwd, -1}, {sp::kBTheta64, o_th64, -1}, {sp::kBLamInv, o_linv, -1}};
+    }
     e = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamCreate"); }
-    // each (stage, build) with work: its LDS, occupancy and persistent grid
-    struct Launch { void (*fn)(const void*, const int2*, int, int*); int grid, nt; size_t lds, items, args; int nit, ctr; };
+    e = hipEventCreateWithFlags(&bp->done, hipEventDisableTiming);
+    if (e != hipSuccess) { delete bp; return hip_fail(e, "hipEventCreate"); }
+    // each (step, build) with work: its LDS, occupancy, persistent grid and work-list counter
+    struct Launch { void (*fn)(const void*, const int2*, int, int*); int grid, nt; size_t lds, items, args; int nit, ctr, norm_slot; };
     std::vector<Launch> launches;
-    for (int stg : stages) {
+    for (const Step& S : steps) {
+        const int stg = S.stg;
         const bool is_theta = stg == sp::kBTheta64 || stg == sp::kBThetaFirst || stg == sp::kBThetaResid;
         for (int c = 0; c < kBatchClasses; ++c) {
             const int nit = (int)(is_theta ? th_items[c].size() : lam_items[c].size());
@@ -1937,22 +2050,27 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
             L.lds = lds;
             L.items = is_theta ? o_th_items[c] : o_lam_items[c];
             L.nit = nit;
-            L.ctr = stg * kBatchClasses + c;
-            L.args = stg == sp::kBLamFwd ? o_lfwd : stg == sp::kBTheta64 ? o_th64 : stg == sp::kBLamInv ? o_linv
-                   : stg == sp::kBThetaFirst ? o_thf : stg == sp::kBThetaResid ? o_thr : o_mix;
+            L.ctr = (int)launches.size();
+            L.args = S.args;
+            L.norm_slot = -1;
             launches.push_back(L);
         }
+        if (S.norm_slot >= 0 && !launches.empty()) launches.back().norm_slot = S.norm_slot;
     }
+    if ((int)launches.size() > kBatchMaxLaunches) { delete bp; return SP_ERR_UNSUPPORTED_SIZE; }
     (void)hipGetLastError();
     e = hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamBeginCapture"); }
     int* ctr = (int*)(B + o_ctr);
     const sp::RhsDesc* dd = (const sp::RhsDesc*)(B + o_desc);
-    hipLaunchKernelGGL(sp::k_batch_reset, dim3(1), dim3(64), 0, bp->cap, ctr, (int)(sp::kBStages * kBatchClasses));
-    for (const Launch& L : launches)
+    hipLaunchKernelGGL(sp::k_batch_reset, dim3(1), dim3(64), 0, bp->cap, ctr, (int)launches.size());
+    for (const Launch& L : launches) {
         hipLaunchKernelGGL(L.fn, dim3(L.grid), dim3(L.nt), L.lds, bp->cap, (const void*)(B + L.args),
                            (const int2*)(B + L.items), L.nit, ctr + L.ctr);
-    if (mixed) hipLaunchKernelGGL(sp::k_batch_norms, dim3(count), dim3(256), 0, bp->cap, dd, (const int*)(B + o_nblk));
+        if (L.norm_slot >= 0)
+            hipLaunchKernelGGL(sp::k_batch_norms, dim3(count), dim3(256), 0, bp->cap, dd, (const int*)(B + o_nblk),
+                               L.norm_slot);
+    }
     e = hipStreamEndCapture(bp->cap, &bp->graph);
     if (e != hipSuccess) { delete bp; return hip_fail(e, "hipStreamEndCapture"); }
     e = hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0);
@@ -1961,49 +2079,132 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     return SP_OK;
 }
 
-bool batch_matches(const BatchPlan* bp, int count, const int* n, const int* m, const double* const* f,
-                   double* const* u, int precision, int dev) {
-    if (!bp || bp->count != count || bp->precision != precision || bp->device != dev) return false;
-    for (int r = 0; r < count; ++r)
-        if (bp->n[r] != n[r] || bp->m[r] != m[r] || bp->f[r] != f[r] || bp->u[r] != u[r]) return false;
-    return true;
-}
 
 }  // namespace
 
-extern "C" int sphere_poisson_solve_batch(int count, const int* n, const int* m, const double* const* f,
-                                          double* const* u, int precision, void* hip_stream, sp_info* infos) {
-    if (count <= 0 || !n || !m || !f || !u) return SP_ERR_INVALID_ARG;
+namespace {
+// Overlaps across a batch: no u[r] may overlap any other buffer of the batch
+// (its own f included); f buffers may overlap each other (they are only
+// read).  The u intervals are sorted and checked pairwise in order; each f
+// interval is then checked against the first u interval ending after its
+// start.  O(count log count), host pointers only.
+bool batch_alias(int count, const int* n, const int* m, const double* const* f, double* const* u) {
+    struct Iv { uintptr_t lo, hi; };
+    std::vector<Iv> us(count);
+    for (int r = 0; r < count; ++r) {
+        const size_t bytes = (size_t)n[r] * m[r] * sizeof(double);
+        us[r] = Iv{(uintptr_t)u[r], (uintptr_t)u[r] + bytes};
+    }
+    std::sort(us.begin(), us.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
+    for (int r = 1; r < count; ++r)
+        if (us[r].lo < us[r - 1].hi) return true;
+    // disjoint and sorted by start, so the ends are sorted too
+    for (int r = 0; r < count; ++r) {
+        const uintptr_t lo = (uintptr_t)f[r], hi = lo + (size_t)n[r] * m[r] * sizeof(double);
+        auto it = std::upper_bound(us.begin(), us.end(), lo, [](uintptr_t v, const Iv& x) { return v < x.hi; });
+        if (it != us.end() && it->lo < hi) return true;
+    }
+    return false;
+}
+}  // namespace
+
+extern "C" int sphere_poisson_batch_plan(sp_batch* out, int count, const int* n, const int* m, const double* const* f,
+                                         double* const* u, const sp_desc* desc, void* hip_stream) {
+    (void)hip_stream;   // the tables are uploaded synchronously
+    if (!out) return SP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count <= 0 || !n || !m || !f || !u || !desc) return SP_ERR_INVALID_ARG;
+    const int precision = desc->precision;
     if (precision != SP_FP64 && precision != SP_MIXED) return SP_ERR_INVALID_ARG;
+    if (desc->flags & ~(SP_SYNC_INFO | SP_AUTOTUNE | SP_INFO)) return SP_ERR_INVALID_ARG;
+    const int R = precision == SP_MIXED ? desc->max_refine : 0;
+    if (precision == SP_MIXED && (R < 1 || R > sp::kBatchMaxRefine)) return SP_ERR_INVALID_ARG;
     for (int r = 0; r < count; ++r) {
         if (!f[r] || !u[r] || n[r] < 4 || (n[r] & 1) || m[r] < 4) return SP_ERR_INVALID_ARG;
-        if (overlap(f[r], u[r], (size_t)n[r] * m[r] * sizeof(double))) return SP_ERR_ALIAS;
+        if (n[r] > (1 << 20) || m[r] > (1 << 20)) return SP_ERR_UNSUPPORTED_SIZE;
     }
+    if (batch_alias(count, n, m, f, u)) return SP_ERR_ALIAS;
+    sp_batch_s* bp = nullptr;
+    const int st = build_batch(count, n, m, f, u, precision, R, desc->tol, (desc->flags & SP_AUTOTUNE) != 0, &bp);
+    if (st != SP_OK) return st;
+    {
+        std::lock_guard<std::mutex> g(g_batches_mu);
+        g_batches.insert(bp);
+    }
+    *out = bp;
+    return SP_OK;
+}
+
+extern "C" int sphere_poisson_solve_batch(sp_batch bp, void* hip_stream, sp_info* infos) {
+    if (!batch_ok(bp)) return SP_ERR_BAD_PLAN;
     hipStream_t s = (hipStream_t)hip_stream;
-    std::lock_guard<std::mutex> g(g_batch_mu);
-    int dev = 0;
-    SP_HIP(hipGetDevice(&dev));
-    if (!batch_matches(g_batch, count, n, m, f, u, precision, dev)) {
-        delete g_batch;
-        g_batch = nullptr;
-        BatchPlan* bp = nullptr;
-        int st = build_batch(count, n, m, f, u, precision, &bp);
-        if (st != SP_OK) return st;
-        g_batch = bp;
-    }
-    SP_HIP(hipGraphLaunch(g_batch->exec, s));
-    if (infos) {
-        SP_HIP(hipStreamSynchronize(s));
-        std::vector<double> sc(4 * (size_t)count);
-        SP_HIP(hipMemcpy(sc.data(), g_batch->scal, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (int r = 0; r < count; ++r) {
-            infos[r].iters = precision == SP_MIXED ? 1 : 0;
-            infos[r].rel_correction = (precision == SP_MIXED && sc[4 * r + 2] > 0.0)
-                                          ? std::sqrt(sc[4 * r + 1] / sc[4 * r + 2]) : 0.0;
-            infos[r].f_integral = sc[4 * r];
-            infos[r].status = SP_OK;
+    SP_HIP(hipGraphLaunch(bp->exec, s));
+    SP_HIP(hipEventRecord(bp->done, s));
+    bp->launched = true;
+    if (!infos) return SP_OK;
+    SP_HIP(hipStreamSynchronize(s));
+    const int count = bp->count, R = bp->max_refine;
+    std::vector<double> sc(sp::kBatchScal * (size_t)count);
+    SP_HIP(hipMemcpy(sc.data(), bp->scal, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    int status = SP_OK;
+    for (int r = 0; r < count; ++r) {
+        const double* q = sc.data() + (size_t)sp::kBatchScal * r;
+        auto rel_of = [&](int it) { return q[2 * it] > 0.0 ? std::sqrt(q[2 * it - 1] / q[2 * it]) : 0.0; };
+        sp_info& in = infos[r];
+        in.iters = R;
+        in.f_integral = q[0];
+        in.rel_residual = 0.0;
+        in.rel_correction = R > 0 ? rel_of(R) : 0.0;
+        // contraction as for a single solve: the ratio of the last two corrections, or the first's own size
+        const double rho = R >= 2 ? (rel_of(R - 1) > 0.0 ? in.rel_correction / rel_of(R - 1) : 0.0) : in.rel_correction;
+        in.est_rel_err = R > 0 ? in.rel_correction * rho : 0.0;
+        in.status = SP_OK;
+        if (R > 0 && bp->tol > 0.0 && !(in.rel_correction <= bp->tol)) {
+            in.status = SP_ERR_NOT_CONVERGED;
+            status = SP_ERR_NOT_CONVERGED;
         }
     }
+    return status;
+}
+
+extern "C" int sphere_poisson_batch_destroy(sp_batch bp) {
+    {
+        std::lock_guard<std::mutex> g(g_batches_mu);
+        if (!bp || !g_batches.erase(bp)) return SP_ERR_BAD_PLAN;
+    }
+    delete bp;   // waits for the last launch
+    return SP_OK;
+}
+
+extern "C" size_t sphere_poisson_stream_partials(size_t count) {
+    return (count + sp::kStreamChunk - 1) / sp::kStreamChunk;
+}
+
+extern "C" int sphere_poisson_stream(int kind, const double* x, double* y, size_t count, void* hip_stream) {
+    const int op = kind & 0xf;
+    const bool nt = (kind & SP_STREAM_NONTEMPORAL) != 0;
+    if ((kind & ~(0xf | SP_STREAM_NONTEMPORAL)) || op > SP_STREAM_WRITE) return SP_ERR_INVALID_ARG;
+    if (!y || (op != SP_STREAM_WRITE && !x)) return SP_ERR_INVALID_ARG;
+    if (((uintptr_t)y & 15) || (x && ((uintptr_t)x & 15))) return SP_ERR_INVALID_ARG;
+    if (count == 0) return SP_OK;
+    const size_t blocks = sphere_poisson_stream_partials(count);
+    if (blocks > 0x7fffffffu) return SP_ERR_UNSUPPORTED_SIZE;
+    if (op == SP_STREAM_COPY && overlap(x, y, count * sizeof(double))) return SP_ERR_ALIAS;
+    if (op == SP_STREAM_READ && overlap(x, y, count * sizeof(double), blocks * sizeof(double))) return SP_ERR_ALIAS;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const dim3 grid((unsigned)blocks), block(sp::kStreamThreads);
+    if (op == SP_STREAM_COPY) {
+        if (nt) hipLaunchKernelGGL(sp::k_stream_copy<true>, grid, block, 0, s, x, y, count);
+        else hipLaunchKernelGGL(sp::k_stream_copy<false>, grid, block, 0, s, x, y, count);
+    } else if (op == SP_STREAM_READ) {
+        if (nt) hipLaunchKernelGGL(sp::k_stream_read<true>, grid, block, 0, s, x, y, count);
+        else hipLaunchKernelGGL(sp::k_stream_read<false>, grid, block, 0, s, x, y, count);
+    } else {
+        if (nt) hipLaunchKernelGGL(sp::k_stream_write<true>, grid, block, 0, s, y, 1.0, count);
+        else hipLaunchKernelGGL(sp::k_stream_write<false>, grid, block, 0, s, y, 1.0, count);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "stream kernel launch");
     return SP_OK;
 }
 

@@ -60,8 +60,55 @@ def test_null_plan_calls(lib):
     assert lib.sphere_poisson_solve(bogus, None, None, 0.0, None, None) == 8
 
 
+def _batch(lib, sizes, fptrs, uptrs, prec=1, refine=1, flags=0):
+    k = len(sizes)
+    ns = (ctypes.c_int * k)(*[s[0] for s in sizes])
+    ms = (ctypes.c_int * k)(*[s[1] for s in sizes])
+    fp = (ctypes.c_void_p * k)(*fptrs)
+    up = (ctypes.c_void_p * k)(*uptrs)
+    out = ctypes.c_void_p()
+    d = _desc(0, 0, prec, refine, 0.0, flags)
+    code = lib.sphere_poisson_batch_plan(ctypes.byref(out), k, ns, ms, fp, up, ctypes.byref(d), None)
+    assert not out.value
+    return code
+
+
 def test_batch_argument_validation(lib):
-    assert lib.sphere_poisson_solve_batch(0, None, None, None, None, 0, None, None) == 1
+    """The batch plan validates before any device call; the pointers below
+    are never dereferenced."""
+    out = ctypes.c_void_p()
+    d = _desc(0, 0, 1)
+    assert lib.sphere_poisson_batch_plan(ctypes.byref(out), 0, None, None, None, None, ctypes.byref(d), None) == 1
+    assert lib.sphere_poisson_batch_plan(None, 1, None, None, None, None, ctypes.byref(d), None) == 1
+    MB = 1 << 20
+    a, b, c = 0x10000000, 0x20000000, 0x30000000
+    assert _batch(lib, [(64, 64)], [a], [b], prec=3) == 1                      # precision
+    assert _batch(lib, [(64, 64)], [a], [b], refine=0) == 1                    # mixed needs a correction
+    assert _batch(lib, [(64, 64)], [a], [b], refine=5) == 1                    # at most four
+    assert _batch(lib, [(64, 64)], [a], [b], flags=0x80) == 1                  # unknown flag
+    assert _batch(lib, [(63, 64)], [a], [b]) == 1                              # odd n
+    assert _batch(lib, [(64, 64)], [None], [b]) == 1                           # null pointer
+    # aliasing: a u over its own f, over another problem's f or u; shared f buffers are fine
+    assert _batch(lib, [(64, 64)], [a], [a + 8]) == 6
+    assert _batch(lib, [(64, 64), (64, 64)], [a, b], [c, a + 4096]) == 6       # u1 inside f0
+    assert _batch(lib, [(64, 64), (64, 64)], [a, b], [c, c + 8]) == 6          # u0 and u1 overlap
+    assert _batch(lib, [(64, 64), (128, 64)], [a, c + 64 * 1024 - 8], [c + MB, c]) == 6   # f1 overlaps u1's end
+    assert lib.sphere_poisson_solve_batch(None, None, None) == 8
+    assert lib.sphere_poisson_solve_batch(ctypes.c_void_p(0x1234), None, None) == 8
+    assert lib.sphere_poisson_batch_destroy(None) == 8
+    assert lib.sphere_poisson_get_info(None, None, None) == 8
+
+
+def test_batch_alias_rule_on_disjoint_buffers(lib):
+    """Disjoint outputs and shared inputs pass the alias check: the plan then
+    proceeds to the device and fails there without a GPU (no device), not with
+    SP_ERR_ALIAS."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("with a GPU the plan would be built on these never-launched fake pointers")
+    a, c = 0x10000000, 0x30000000
+    code = _batch(lib, [(64, 64), (64, 64)], [a, a], [c, c + 64 * 64 * 8])
+    assert code not in (1, 6)
 
 
 def test_workspace_bytes_scale(lib):

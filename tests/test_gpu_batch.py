@@ -44,7 +44,8 @@ def test_batch_matches_single_and_oracle(P, precision, tol):
         L = min(n, m) // 4
         fs.append(S.sphere_field(3, 100 + r, n, m, L) + 1e-4 * S.noise(3, 100 + r, (m, n), 1.0))
     fg = [gpu(f) for f in fs]
-    us = [host(u) for u in P.solve_batch(fg, precision)]
+    batch = P.SpherePoissonBatch(fg, precision=precision)
+    us = [host(u) for u in batch.solve()]
     for r, (f, u) in enumerate(zip(fs, us)):
         m, n = f.shape
         plan = P.SpherePoisson(n, m, precision)
@@ -54,8 +55,9 @@ def test_batch_matches_single_and_oracle(P, precision, tol):
         # spectrum layout (different rounding order, same solution)
         assert rel2(u, single) <= (1e-13 if precision == "fp64" else 1e-12), (r, n, m)
         assert rel2(u, O.solve_reduced(f)) <= tol, (r, n, m)
-    # a second call with the same sizes and pointers replays the cached graph
-    again = [host(u) for u in P.solve_batch(fg, precision)]
+    # a second launch of the same plan replays the graph bitwise
+    again = [host(u) for u in batch.solve()]
+    batch.close()
     for a, b in zip(us, again):
         assert np.array_equal(a, b)
 
@@ -89,3 +91,53 @@ def test_c3_batch_512(P):
     assert max(errs) <= 1e-10
     for r in range(0, 512, 32):
         assert rel2(us[r], O.solve_reduced(fs[r])) <= 1e-10, r
+
+
+def test_batch_corrections_and_infos(P):
+    """max_refine = 2 runs the correction stages twice in the graph: the
+    second correction is smaller than the first, both iterates stay within the
+    bar, and the infos report the iterations, the correction, the error
+    estimate and the integral of f; tol below the last correction marks a
+    problem not converged (the outputs are still written)."""
+    sizes = [(128, 192), (256, 195), (192, 128), (320, 448)]
+    fs = [S.sphere_field(3, 300 + r, n, m, min(n, m) // 4) for r, (n, m) in enumerate(sizes)]
+    fg = [gpu(f) for f in fs]
+    b1 = P.SpherePoissonBatch(fg, precision="mixed", max_refine=1)
+    u1, i1 = b1.solve(with_info=True)
+    u1 = [host(u) for u in u1]
+    b1.close()
+    b2 = P.SpherePoissonBatch(fg, precision="mixed", max_refine=2)
+    u2, i2 = b2.solve(with_info=True)
+    u2 = [host(u) for u in u2]
+    b2.close()
+    for r, f in enumerate(fs):
+        ref = O.solve_reduced(f)
+        assert rel2(u1[r], ref) <= 1e-10 and rel2(u2[r], ref) <= 1e-10, r
+        assert i1[r]["iters"] == 1 and i2[r]["iters"] == 2
+        assert i2[r]["rel_correction"] < i1[r]["rel_correction"]
+        assert 0.0 < i1[r]["est_rel_err"] < 1e-9
+        assert i1[r]["status"] == 0 and i2[r]["status"] == 0
+        assert abs(i1[r]["f_integral"]) < 1e-10          # band-limited fields with l >= 1
+    bt = P.SpherePoissonBatch(fg, precision="mixed", max_refine=1, tol=1e-30)
+    ut, it = bt.solve(with_info=True)
+    ut = [host(u) for u in ut]
+    bt.close()
+    assert all(i["status"] == 5 for i in it)
+    for r in range(len(fs)):
+        assert np.array_equal(ut[r], u1[r])
+
+
+def test_batch_plan_allocates_once_and_rejects_cross_aliasing(P):
+    """Solves on a batch plan reuse its graph (no new plan per call); an output
+    overlapping another problem's input is rejected before any device work."""
+    a = gpu(np.zeros((64, 64)))
+    b = gpu(np.zeros((64, 64)))
+    with pytest.raises(P.SpError) as e:
+        P.SpherePoissonBatch([a, b], outs=[torch.empty_like(a), a])
+    assert e.value.code == 6
+    f = gpu(S.sphere_field(3, 7, 64, 48, 12))
+    batch = P.SpherePoissonBatch([f, f], precision="fp64")     # shared inputs are allowed
+    u0 = [host(u).copy() for u in batch.solve()]
+    u1 = [host(u) for u in batch.solve()]
+    batch.close()
+    assert np.array_equal(u0[0], u0[1]) and np.array_equal(u1[0], u0[0])

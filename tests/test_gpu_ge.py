@@ -155,7 +155,7 @@ def test_paper_printed_ranks_and_poisson(P, name):
         f = np.sin(50 * x * y * z)
     else:
         f = np.cos(1 + 2 * np.pi * (x + y) + 5 * np.sin(np.pi * z))
-    d, c, r, piv = P.ge_lowrank(gpu(f), 40, 0.01, 5e-13)
+    d, c, r, piv = P.ge_lowrank(gpu(f), 30, 0.01, 5e-13)   # 60 terms at most: the solve takes rank <= m
     dh = d.cpu().numpy()
     assert np.count_nonzero(dh) == g["paper_printed_rank"]
     rec = OL.lowrank_grid(dh, c.cpu().numpy(), r.cpu().numpy())

@@ -83,6 +83,54 @@ def test_mixed_info_and_two_corrections(P):
     assert rel2(u1, ref) <= TOL_MIXED and rel2(u2, ref) <= TOL_MIXED
 
 
+@pytest.mark.parametrize("odd_m", [False, True])
+def test_mixed_residual_and_error_estimate(P, odd_m):
+    """rel_residual is the float64 residual norm of the iterate the last
+    correction was formed from, relative to F: after the float32 solve it is
+    far above the iterate's error (the operator's entries grow as q^2, so the
+    float32 transforms' rounding in high coefficients dominates it), and it
+    drops by the size of a correction once one has been applied; est_rel_err bounds the
+    measured error of the returned u within a factor of 100.  The same info
+    comes from sphere_poisson_get_info after an SP_INFO solve (no
+    synchronisation inside the solve); without SP_INFO / SP_SYNC_INFO the
+    norms read -1."""
+    n, m = (512, 385) if odd_m else (512, 384)
+    f = S.sphere_field(23, 1, n, m, 120)
+    ref = O.solve_reduced(f)
+    u1, i1 = run(P, f, max_refine=1, sync_info=True)
+    u2, i2 = run(P, f, max_refine=2, sync_info=True)
+    assert 1e-8 < i1.rel_residual < 1e-1
+    assert i2.rel_residual < 1e-3 * i1.rel_residual
+    for u, i in ((u1, i1), (u2, i2)):
+        err = rel2(u, ref)
+        assert 0.0 < i.est_rel_err < 1e-10
+        assert err <= 100.0 * i.est_rel_err + 1e-14
+    plan = P.SpherePoisson(n, m, "mixed", max_refine=1, collect_info=True)
+    ud = host(plan.solve(gpu(f)))
+    gi = plan.get_info()
+    plan.close()
+    assert np.array_equal(ud, u1)
+    assert gi["iters"] == 1 and gi["status"] == 0
+    assert gi["rel_residual"] == pytest.approx(i1.rel_residual, rel=1e-12)
+    assert gi["est_rel_err"] == pytest.approx(i1.est_rel_err, rel=1e-12)
+    plan = P.SpherePoisson(n, m, "mixed", max_refine=1)
+    plan.solve(gpu(f))
+    gi = plan.get_info()
+    plan.close()
+    assert gi["rel_correction"] == -1.0 and gi["rel_residual"] == -1.0 and gi["est_rel_err"] == -1.0
+    assert abs(gi["f_integral"]) < 1e-10
+
+
+def test_mixed_adjoint_rejects_two_corrections(P):
+    """The mixed adjoint supports one correction: max_refine = 2 is an argument
+    error, not a silent clamp."""
+    plan = P.SpherePoisson(64, 48, "mixed", max_refine=2)
+    with pytest.raises(P.SpError) as e:
+        plan.adjoint(gpu(np.ones((48, 64))))
+    assert e.value.code == 1
+    plan.close()
+
+
 @pytest.mark.parametrize("c", [0.0, 2.0])
 def test_mixed_integral_constraint(P, c):
     f, u_exact = S.sphere_field(24, 0, 96, 64, 20, with_solution=True)
