@@ -416,10 +416,12 @@ def bench_c4(args, P, S, torch, np, count=16, n=2048, L=512):
     return res
 
 
-def bench_sweep(args, P, S, torch, np, sizes=(1024, 2048, 4096, 10000)):
+def bench_sweep(args, P, S, torch, np, sizes=(1024, 2048, 4096, 6144, 8192, 10000)):
     """Time per solve against the number of unknowns, n = m (the paper's
     complexity experiment, Section 5, Figure FastSphericalPoissonSolver right):
-    both precisions, and the least-squares slope of log time against log(nm)."""
+    both precisions, and the least-squares slope of log time against log(nm),
+    over all sizes and over those from 4096 on (below that a solve does not
+    fill the chip and fixed costs flatten the curve)."""
     res = {"workload": "sweep_n_eq_m", "sizes": list(sizes)}
     for prec in ("fp64", "mixed"):
         ms_list = []
@@ -444,9 +446,12 @@ def bench_sweep(args, P, S, torch, np, sizes=(1024, 2048, 4096, 10000)):
         x = np.log([float(n) * n for n in sizes])
         y = np.log(ms_list)
         slope = float(np.polyfit(x, y, 1)[0])
-        log("bench: sweep %s ms %s, slope %.3f" % (prec, ["%.3f" % t for t in ms_list], slope))
+        big = [i for i, n in enumerate(sizes) if n >= 4096]
+        slope_big = float(np.polyfit(x[big], y[big], 1)[0])
+        log("bench: sweep %s ms %s, slope %.3f (n >= 4096: %.3f)" % (prec, ["%.3f" % t for t in ms_list], slope,
+                                                                      slope_big))
         res[prec] = {"ms_per_solve": ms_list, "dof_per_s": [n * n / (t * 1e-3) for n, t in zip(sizes, ms_list)],
-                     "loglog_slope": slope}
+                     "loglog_slope": slope, "loglog_slope_n_ge_4096": slope_big}
     return res
 
 

@@ -273,6 +273,16 @@ __device__ __forceinline__ void dft(Cx<T>* v) {
     }
 }
 
+// ---------------------------------------------------------------- barriers
+// A workgroup barrier for LDS traffic: it waits for this wave's LDS operations
+// only.  __syncthreads() also waits for every global load and store the wave
+// has in flight, which would stall the transform passes on memory traffic
+// issued before them (a persistent kernel's loads of its next block, the
+// stores of its last one).  The "memory" clobber keeps the compiler from
+// moving memory accesses across it.  Callers that hand global memory from one
+// thread to another use __syncthreads().
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ---------------------------------------------------------------- plans
 constexpr int kMaxPass = 16;
 
@@ -317,7 +327,7 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -342,7 +352,7 @@ __device__ __forceinline__ void stockham_pass(Cx<T>* __restrict__ buf, int N, in
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // ---------------------------------------------------------------- fixed-size transforms
@@ -366,7 +376,7 @@ __device__ __forceinline__ void stockham_pass_ct(Cx<T>* __restrict__ buf, const 
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -388,7 +398,7 @@ __device__ __forceinline__ void stockham_pass_ct(Cx<T>* __restrict__ buf, const 
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 template <typename T, bool INV, int N, int NT, int NS, int R, int... REST>

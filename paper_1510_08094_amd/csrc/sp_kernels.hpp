@@ -49,10 +49,11 @@ __device__ __forceinline__ size_t spec_at(int j, int k, int N, int lay) {
 // blocks, the g blocks of a run go to consecutive workgroups of one XCD
 // (workgroups are dealt round-robin over the 8 XCDs), so their writes to the
 // same 128-byte lines meet in that XCD's L2.  The grid is a multiple of 8 g.
-__device__ __forceinline__ int lambda_tile(int glog2) {
-    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+__device__ __forceinline__ int lambda_tile_of(int tile, int glog2) {
+    const int x = tile & 7, i = tile >> 3;
     return ((x + ((i >> glog2) << 3)) << glog2) + (i & ((1 << glog2) - 1));
 }
+__device__ __forceinline__ int lambda_tile(int glog2) { return lambda_tile_of(blockIdx.x, glog2); }
 
 // Split the length-N complex DFT of every row into the half spectrum X_0..X_N
 // (times w_mid for 0<k<N, w_end for k in {0, N}) and store it (type TS).
@@ -92,42 +93,60 @@ __device__ __forceinline__ void r2c_split_store(const Cx<T>* lines, size_t strid
 // the length-N complex sequence whose inverse DFT interleaves the real output.
 // DLAM: the spectrum of d/dlambda instead, coefficient k times i k; the k = 0
 // and k = n/2 terms vanish (the derivative of the real Nyquist mode is zero on
-// the grid).
+// the grid).  Element e of a thread's share (e = threadIdx.x + it blockDim.x
+// < (N/2 + 1) RW, the row fastest) is the pair (k, N - k) of row e mod RW;
+// c2r_fetch loads those pairs, c2r_build forms the two line entries.
+template <typename TS>
+__device__ __forceinline__ void c2r_fetch(const Cx<TS>* spec, int N, int rwl, int lay, int m, int jb, int e,
+                                          Cx<TS>& sk, Cx<TS>& sn) {
+    const int jj = e & ((1 << rwl) - 1);
+    const int k = e >> rwl;
+    const int j = (jb << rwl) + jj;
+    if (j >= m) return;
+    sk = spec[spec_at(j, k, N, lay)];
+    sn = spec[spec_at(j, k == 0 ? N : N - k, N, lay)];
+}
+
+template <typename T, typename TS, bool DLAM = false>
+__device__ __forceinline__ void c2r_build(Cx<T>* lines, size_t stride, const Cx<T>* tw, int N, int rwl, int m,
+                                          int jb, int e, Cx<TS> sk, Cx<TS> sn, T w_mid, T w_end) {
+    const int jj = e & ((1 << rwl) - 1);
+    const int k = e >> rwl;
+    const int j = (jb << rwl) + jj;
+    if (j >= m) return;
+    Cx<T>* b = lines + (size_t)jj * stride;
+    if (k == 0) {
+        if constexpr (DLAM) {
+            b[0] = Cx<T>{(T)0, (T)0};
+        } else {
+            const T x0 = (T)sk.x * w_end;
+            const T xN = (T)sn.x * w_end;
+            b[0] = Cx<T>{x0 + xN, x0 - xN};
+        }
+        return;
+    }
+    Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
+    Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
+    if constexpr (DLAM) {
+        xk = mul_i(xk) * (T)k;
+        xn = mul_i(xn) * (T)(N - k);
+    }
+    const Cx<T> P = xk + cconj(xn);
+    const Cx<T> Q = xk - cconj(xn);
+    const Cx<T> iWQ = mul_i(cmulc(Q, tw[k]));   // i conj(W) Q
+    b[k] = P + iWQ;
+    if (N - k != k) b[N - k] = cconj(P - iWQ);
+}
+
 template <typename T, typename TS, bool DLAM = false>
 __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, const Cx<TS>* spec,
                                                  const Cx<T>* tw, int N, int rwl, int lay, int m, int jb,
                                                  T w_mid, T w_end) {
-    const int rw = 1 << rwl;
-    const int npairs = N / 2 + 1;
-    for (int e = threadIdx.x; e < npairs * rw; e += blockDim.x) {
-        const int jj = e & (rw - 1);
-        const int k = e >> rwl;
-        const int j = (jb << rwl) + jj;
-        if (j >= m) continue;
-        Cx<T>* b = lines + (size_t)jj * stride;
-        if (k == 0) {
-            if constexpr (DLAM) {
-                b[0] = Cx<T>{(T)0, (T)0};
-            } else {
-                const T x0 = (T)spec[spec_at(j, 0, N, lay)].x * w_end;
-                const T xN = (T)spec[spec_at(j, N, N, lay)].x * w_end;
-                b[0] = Cx<T>{x0 + xN, x0 - xN};
-            }
-            continue;
-        }
-        const Cx<TS> sk = spec[spec_at(j, k, N, lay)];
-        const Cx<TS> sn = spec[spec_at(j, N - k, N, lay)];
-        Cx<T> xk = Cx<T>{(T)sk.x, (T)sk.y} * w_mid;
-        Cx<T> xn = Cx<T>{(T)sn.x, (T)sn.y} * w_mid;
-        if constexpr (DLAM) {
-            xk = mul_i(xk) * (T)k;
-            xn = mul_i(xn) * (T)(N - k);
-        }
-        const Cx<T> P = xk + cconj(xn);
-        const Cx<T> Q = xk - cconj(xn);
-        const Cx<T> iWQ = mul_i(cmulc(Q, tw[k]));   // i conj(W) Q
-        b[k] = P + iWQ;
-        if (N - k != k) b[N - k] = cconj(P - iWQ);
+    const int total = (N / 2 + 1) << rwl;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        Cx<TS> sk{}, sn{};
+        c2r_fetch<TS>(spec, N, rwl, lay, m, jb, e, sk, sn);
+        c2r_build<T, TS, DLAM>(lines, stride, tw, N, rwl, m, jb, e, sk, sn, w_mid, w_end);
     }
 }
 
@@ -610,7 +629,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
         const int q = C.q0 + 2 * row;
         r[ii] = load(lpos(q), q, cnt > 0 ? slot0 + iic * C.p : A.s * A.p, ii < cnt);
     }
-    __syncthreads();   // B1: the line may now be overwritten by scratch
+    lds_barrier();   // B1: the line may now be overwritten by scratch
 
     // top-down: x_ii = dy - S dv - cp x_{ii+1}; at the last interior row
     // x = yL - S vL - S+ wL
@@ -661,7 +680,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     T* be = al + ptot;
     T* ga = be + ptot;
     if (cnt > 0) { de[tid] = yL; al[tid] = vL; ga[tid] = wL; }
-    __syncthreads();   // B2
+    lds_barrier();   // B2
     T nal = 0, nbe = 1, nga = 0;
     V nde{};
     if (cnt > 0) {
@@ -675,9 +694,9 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
         nga = -c0 * wF;
         nde = r[0] - pyL * a0 - yF * c0;
     }
-    __syncthreads();   // B3
+    lds_barrier();   // B3
     if (cnt > 0) { al[tid] = nal; be[tid] = nbe; ga[tid] = nga; de[tid] = nde; }
-    __syncthreads();   // B4
+    lds_barrier();   // B4
     // parallel cyclic reduction on the separators of each class
     const int pmax = max(A.p, B.p);
     for (int h = 1; h < pmax; h <<= 1) {
@@ -702,17 +721,17 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
                 xga = 0;
             }
         }
-        __syncthreads();
+        lds_barrier();
         nal = xal; nbe = xbe; nga = xga; nde = xde;
         if (cnt > 0) { al[tid] = nal; be[tid] = nbe; ga[tid] = nga; de[tid] = nde; }
-        __syncthreads();
+        lds_barrier();
     }
     const V S = nde * rcp_pivot(nbe);
     if (cnt > 0) de[tid] = S;
-    __syncthreads();
+    lds_barrier();
     V Sn{};
     if (cnt > 0 && tid + 1 < cls_hi) Sn = de[tid + 1];
-    __syncthreads();   // scratch no longer needed: write the solution
+    lds_barrier();   // scratch no longer needed: write the solution
     if (cnt > 0) {
         store(lpos(C.q0 + 2 * lo), S);
         // interior rows with both separators known: forward, then backward substitution
@@ -758,11 +777,11 @@ __device__ __forceinline__ Cx<double> block_sum(Cx<double> v, Cx<double>* red) {
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
-    __syncthreads();
+    lds_barrier();
     Cx<double> s{0.0, 0.0};
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 0; w < nw; ++w) s = s + red[w];
-    __syncthreads();
+    lds_barrier();
     return s;
 }
 __device__ __forceinline__ double block_sum(double v, Cx<double>* red) {
@@ -785,7 +804,7 @@ __device__ __forceinline__ void scan_affine(VD& A, double& Bm, unsigned char* sc
     VD* sa = reinterpret_cast<VD*>(scratch);
     double* sb = reinterpret_cast<double*>(sa + ptot);
     if (valid) { sa[tid] = A; sb[tid] = Bm; }
-    __syncthreads();
+    lds_barrier();
     const int pmax = ptot;   // upper bound on class length
     for (int h = 1; h < pmax; h <<= 1) {
         VD nA = A;
@@ -798,10 +817,10 @@ __device__ __forceinline__ void scan_affine(VD& A, double& Bm, unsigned char* sc
                 nB = Bm * sb[o];
             }
         }
-        __syncthreads();
+        lds_barrier();
         A = nA; Bm = nB;
         if (valid) { sa[tid] = A; sb[tid] = Bm; }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -843,7 +862,7 @@ __device__ __forceinline__ void solve_k0_io(Load&& load, Store&& store, unsigned
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     auto sub_of = [&](int row) -> double {   // sub-diagonal of row `row` of the class
         if (row <= 0) return 0.0;
         const double q = (double)(C.q0 + 2 * row);
@@ -869,7 +888,7 @@ __device__ __forceinline__ void solve_k0_io(Load&& load, Store&& store, unsigned
     VD* sa = reinterpret_cast<VD*>(scratch);
     VD zin{};
     if (cnt > 0 && tid - 1 >= cls_lo) zin = sa[tid - 1];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int ii = 0; ii < SMAX; ++ii) {
         if (ii < cnt) {
@@ -900,7 +919,7 @@ __device__ __forceinline__ void solve_k0_io(Load&& load, Store&& store, unsigned
     scan_affine<VD, SMAX>(Ab, Bb, scratch, tid, cls_lo, cls_hi, ptot, true, cnt > 0);
     VD xin{};
     if (cnt > 0 && tid + 1 < cls_hi) xin = sa[tid + 1];
-    __syncthreads();
+    lds_barrier();
     VD part{};
 #pragma unroll
     for (int ii = SMAX - 1; ii >= 0; --ii) {

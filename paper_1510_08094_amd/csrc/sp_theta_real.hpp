@@ -60,7 +60,7 @@ __device__ __forceinline__ void rdct_split_forward(Cx<T>* z, const Cx<T>* __rest
             o[e][3] = -Wqq.y;
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int e = 0; e < kRealPairHold; ++e) {
         const int q = tid + e * nthr;
@@ -73,7 +73,7 @@ __device__ __forceinline__ void rdct_split_forward(Cx<T>* z, const Cx<T>* __rest
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // y (m reals, position order; coefficient q times s0 / s1) -> Z (M complex), in place.
@@ -100,7 +100,7 @@ __device__ __forceinline__ void rdct_split_inverse(T* y, const Cx<T>* __restrict
             o[e][1] = cconj(Pp - iwQ);
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int e = 0; e < kRealPairHold; ++e) {
         const int q = tid + e * nthr;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void rdct_split_inverse(T* y, const Cx<T>* __restrict
             if (q != 0 && M - q != q) z[M - q] = o[e][1];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 __device__ __forceinline__ int line_pos(int j, int m) { return (j & 1) ? m - ((j + 1) >> 1) : (j >> 1); }
@@ -202,7 +202,7 @@ __device__ __forceinline__ void theta_real_body(const ThetaArgs<T>& a, int k, in
         const bool tr = a.mode == kSolveTransposed;
         if (k == 0) solve_k0<T, SMAX>(y, smem_raw, m, tr, part == 0 ? a.c0 : 0.0, a.k0tab, red, tid);
         else solve_partitioned<T, SMAX>(y, smem_raw, m, k, sine, tr, tid);
-        __syncthreads();
+        lds_barrier();
     }
     rdct_split_inverse<T>(y, a.eq, a.ws, m, scale ? (T)m : (T)1, scale ? (T)m * (T)0.5 : (T)1, tid, nthr);
     fft_lds<T, true, EPT, RMAX>(z, 0, a.fft, a.tw, tid, a.nthr_fft, tid < a.nthr_fft);
@@ -269,7 +269,7 @@ __device__ __forceinline__ void theta_mixed_real_k0(const ThetaMixArgs& a, int p
     };
     auto store = [&](int q, double x) { yf[q] = (float)((TRANS && RESID && q == 0) ? -x0_pin : x); };
     solve_k0_io<double, SMAXD, double>(load, store, smem_raw, m, TRANS, r0, a.k0tab, red, tid);
-    __syncthreads();
+    lds_barrier();
 }
 
 // Same refinement as theta_mixed_body, on one real part: float64 analysis
@@ -331,7 +331,7 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
                 [&](int p, int q, int slot, bool own) { return (float)load(p, q, slot, own); },
                 [&](int p, float x) { yf[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
         }
-        __syncthreads();
+        lds_barrier();
     } else {
         theta_mixed_real_k0<SMAXD, RESID, TRANS>(a, part, yd, yf, Fk, smem_raw, red, tid, acc_r, acc_f);
     }

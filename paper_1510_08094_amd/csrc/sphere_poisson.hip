@@ -238,6 +238,10 @@ struct sp_plan_s {
     int rw_log2 = 0;          // rows per lambda workgroup (log2)
     int lay_log2 = 0;         // spectrum run length (log2)
     int lam_grid = 0;         // lambda workgroups (a multiple of 8 runs when a run spans several)
+    // forward lambda passes: half the rows per workgroup when a full tile leaves room for one
+    // workgroup per compute unit only, so that two share it (one loads while the other computes)
+    int fwd_rw_log2 = 0, fwd_grid = 0;
+    size_t fwd_lds = 0;
     int lam_threads = 0;      // threads per row in the lambda kernels
     int theta_threads = 0;    // block size of the theta kernel
     int theta_fft_threads = 0;
@@ -604,6 +608,17 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
             if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
+    // forward lambda passes: when a tile of the plan's rows fills the LDS so that one workgroup
+    // runs per compute unit, the forward pass takes half the rows (measured at n = m = 10^4:
+    // 0.53 -> 0.47 ms); the passes that read a spectrum keep the full tile, whose reads take
+    // whole runs
+    p->fwd_rw_log2 = p->rw_log2;
+    if (p->rw_log2 > 0 && 2 * p->lam_lds + static_lds > lds_limit) p->fwd_rw_log2 = p->rw_log2 - 1;
+    p->fwd_lds = ((size_t)N << p->fwd_rw_log2) * sizeof(Cx<double>);
+    {
+        const int nblk = (m + (1 << p->fwd_rw_log2) - 1) >> p->fwd_rw_log2;
+        p->fwd_grid = round_up(nblk, 8 << (p->lay_log2 - p->fwd_rw_log2));
+    }
     // gradient pass: two float64 lines per row, as many rows per workgroup as fit (at most the plan's);
     // the theta division by sin(theta) needs one thread per chunk of each parity class
     const int div_hold = p->theta_real ? sp::kRealLoadHold : sp::kThetaHold;
@@ -1088,6 +1103,15 @@ bool overlap(const void* a, const void* b, size_t abytes, size_t bbytes) {
     return x < y + bbytes && y < x + abytes;
 }
 
+// The forward lambda pass (rows -> spectrum in runs of 8 rows) with the
+// plan's forward tile.
+template <typename T>
+void launch_lambda_fwd(sp_plan p, void (*fn)(sp::LambdaArgs<T>), sp::LambdaArgs<T> a, hipStream_t s) {
+    a.rw_log2 = p->fwd_rw_log2;
+    hipLaunchKernelGGL(fn, dim3(p->fwd_grid), dim3(round_up((1 << p->fwd_rw_log2) * p->lam_threads, 64)), p->fwd_lds,
+                       s, a);
+}
+
 // One FP64 pass over the three kernels: lambda forward, theta, lambda inverse.
 int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool fwd_sin2,
              bool adjoint_weights, bool want_fint, hipStream_t s) {
@@ -1108,7 +1132,7 @@ int run_fp64(sp_plan p, const double* in, double* out, int mode, double c0, bool
     else { la.w_mid = 2.0; la.w_end = 1.0; }
     if (in) {
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
-        hipLaunchKernelGGL(p->kd.fwd, dim3(p->lam_grid), dim3(round_up(rw * p->lam_threads, 64)), p->lam_lds, s, la);
+        launch_lambda_fwd(p, p->kd.fwd, la, s);
     }
     // theta
     sp::ThetaArgs<double> ta{};
@@ -1210,7 +1234,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
     la.w_end = adjoint ? 1.0 : 1.0 / n;
     if (f) {   // f == nullptr: spec64 already holds the right-hand side's spectrum
         ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
-        hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
+        launch_lambda_fwd(p, p->kd.fwd, la, s);
     }
     // 2. first solve
     sp::ThetaMixArgs ta{};
@@ -1272,7 +1296,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
                 if (adjoint) return SP_ERR_INVALID_ARG;   // checked by the caller: adjoint uses one correction
                 la.x = u; la.spec = p->specB; la.rowscale = nullptr;
                 ProfScope ps(p, SP_KERNEL_LAMBDA_FWD, s);
-                hipLaunchKernelGGL(p->kd.fwd, lam_grid, lam_block, p->lam_lds, s, la);
+                launch_lambda_fwd(p, p->kd.fwd, la, s);
             }
             // the last correction pass also sums the residual of its iterate (info builds)
             const bool norm = want && it == R;
