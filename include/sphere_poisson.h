@@ -219,6 +219,25 @@ int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int st
                               void* work, size_t work_bytes, double* d, double* c, double* r, int* pivots,
                               void* hip_stream);
 
+/* For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same elimination as sphere_poisson_ge_lowrank, same arguments, layout and
+ * results, but with no workspace argument.  The workspace is a static device
+ * array of the library, SP_GE_STATIC_BYTES (40 MiB) on every device it runs
+ * on, held until the process ends; the call allocates and frees nothing (its
+ * first call on a device only looks up that array's address).  Grids whose
+ * workspace, sphere_poisson_ge_workspace_bytes(n, m), exceeds SP_GE_STATIC_BYTES
+ * (about 5.2 million samples, e.g. 2048 x 2048 fits) give
+ * SP_ERR_UNSUPPORTED_SIZE.  Every call on one device shares that array, which
+ * keeps the last call's contents (each call writes every part it reads before
+ * reading it): calls that overlap on one device race, so issue them on one
+ * stream or serialise them.
+ * Errors: as sphere_poisson_ge_lowrank, plus SP_ERR_UNSUPPORTED_SIZE and
+ * SP_ERR_NO_DEVICE. */
+#define SP_GE_STATIC_BYTES (40u << 20)
+int sphere_poisson_ge_lowrank_static(int n_lambda, int m_theta, const double* f, int steps, double alpha, double tol,
+                                     double* d, double* c, double* r, int* pivots, void* hip_stream);
+
 /* Euclidean transpose of the linear map f -> u (integral = 0) on the grid
  * samples: fbar = S^T g.  This is the reverse-mode derivative of the solve
  * for any loss; same layout, ownership and errors as sphere_poisson_solve.

@@ -86,6 +86,7 @@ def library():
     lib.sphere_poisson_ge_workspace_bytes.argtypes = [ci, ci]
     lib.sphere_poisson_ge_workspace_bytes.restype = ctypes.c_size_t
     lib.sphere_poisson_ge_lowrank.argtypes = [ci, ci, vp, ci, cd, cd, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
+    lib.sphere_poisson_ge_lowrank_static.argtypes = [ci, ci, vp, ci, cd, cd, vp, vp, vp, vp, vp]
     lib.sphere_poisson_batch_plan.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                               ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SpDesc), vp]
     lib.sphere_poisson_solve_batch.argtypes = [vp, vp, ctypes.POINTER(SpInfo)]
@@ -114,7 +115,7 @@ def library():
                  "sphere_poisson_transform_roundtrip", "sphere_poisson_tangential_gradient",
                  "sphere_poisson_curl_scalar", "sphere_poisson_divergence", "sphere_poisson_curl",
                  "sphere_poisson_vorticity", "sphere_poisson_integral", "sphere_poisson_solve_lowrank",
-                 "sphere_poisson_eval_lowrank", "sphere_poisson_ge_lowrank"):
+                 "sphere_poisson_eval_lowrank", "sphere_poisson_ge_lowrank", "sphere_poisson_ge_lowrank_static"):
         getattr(lib, name).restype = ci
     _lib = lib
     return lib

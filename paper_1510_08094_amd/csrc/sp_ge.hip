@@ -19,6 +19,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "../../include/sphere_poisson.h"
 
@@ -227,27 +229,42 @@ extern "C" size_t sphere_poisson_ge_workspace_bytes(int n_lambda, int m_theta) {
     return ge_layout(n_lambda, m_theta).total;
 }
 
-extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int steps, double alpha,
-                                         double tol, void* work, size_t work_bytes, double* d, double* c, double* r,
-                                         int* pivots, void* hip_stream) {
-    const int n = n_lambda, m = m_theta;
+namespace {
+
+// Validation common to both entry points: sizes, parameters, outputs (and,
+// when given, the caller's workspace) before any device call.
+int ge_check(int n, int m, const double* f, int steps, double alpha, double tol, const void* work, size_t work_bytes,
+             const double* d, const double* c, const double* r, const int* pivots) {
     if (!ge_sizes_ok(n, m) || steps < 1 || !(alpha >= 0.0 && alpha <= 1.0) || !(tol >= 0.0)) return SP_ERR_INVALID_ARG;
-    if (!f || !work || !d || !c || !r) return SP_ERR_INVALID_ARG;
+    if (!f || !d || !c || !r) return SP_ERR_INVALID_ARG;
+    if ((uintptr_t)r & 15) return SP_ERR_INVALID_ARG;   // double2 access to the rows
     const GeLayout L = ge_layout(n, m);
-    if (work_bytes < L.total) return SP_ERR_INVALID_ARG;
-    if (((uintptr_t)work | (uintptr_t)r) & 15) return SP_ERR_INVALID_ARG;   // double2 access to the grid and rows
+    if (work) {
+        if (work_bytes < L.total) return SP_ERR_INVALID_ARG;
+        if ((uintptr_t)work & 15) return SP_ERR_INVALID_ARG;   // double2 access to the grid
+    }
     const size_t fb = (size_t)n * m * sizeof(double);
     const size_t db = 2 * (size_t)steps * sizeof(double), cb = db * m, rb = db * n, pb = 2 * (size_t)steps * sizeof(int);
     const void* outs[4] = {d, c, r, pivots};
     const size_t ob[4] = {db, cb, rb, pivots ? pb : 0};
     for (int a = 0; a < 4; ++a) {
         if (!outs[a]) continue;
-        if (!disjoint(outs[a], ob[a], f, fb) || !disjoint(outs[a], ob[a], work, L.total)) return SP_ERR_ALIAS;
+        if (!disjoint(outs[a], ob[a], f, fb)) return SP_ERR_ALIAS;
+        if (work && !disjoint(outs[a], ob[a], work, L.total)) return SP_ERR_ALIAS;
         for (int b = a + 1; b < 4; ++b)
             if (outs[b] && !disjoint(outs[a], ob[a], outs[b], ob[b])) return SP_ERR_ALIAS;
     }
-    if (!disjoint(f, fb, work, L.total)) return SP_ERR_ALIAS;
-    hipStream_t s = (hipStream_t)hip_stream;
+    if (work && !disjoint(f, fb, work, L.total)) return SP_ERR_ALIAS;
+    return SP_OK;
+}
+
+// The elimination in a workspace of ge_layout(n, m).total bytes (every part of
+// it is written before it is read: the residual by the copy of f, the partials
+// by the first search, the record by the first pivot).
+int ge_run(int n, int m, const double* f, int steps, double alpha, double tol, void* work, double* d, double* c,
+           double* r, int* pivots, hipStream_t s) {
+    const GeLayout L = ge_layout(n, m);
+    const size_t fb = (size_t)n * m * sizeof(double);
     unsigned char* w = static_cast<unsigned char*>(work);
     double* e = reinterpret_cast<double*>(w + L.off_e);
     double* ps = reinterpret_cast<double*>(w + L.off_score);
@@ -267,4 +284,60 @@ extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double
     }
     if (hipGetLastError() != hipSuccess) return SP_ERR_HIP;
     return SP_OK;
+}
+
+// The workspace of sphere_poisson_ge_lowrank_static: a file-scope device
+// array, one copy on every device the library runs on, held until the
+// process ends.  Host code never passes the array's name to a kernel (that is
+// a host-side stand-in): it takes the array's device address once per device,
+// with that device current, and uses that address.
+constexpr size_t kGeStaticBytes = SP_GE_STATIC_BYTES;
+__device__ __align__(256) unsigned char scratch[kGeStaticBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its scratch
+
+int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SP_ERR_NO_DEVICE;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return SP_OK;
+    }
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return SP_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" int sphere_poisson_ge_lowrank(int n_lambda, int m_theta, const double* f, int steps, double alpha,
+                                         double tol, void* work, size_t work_bytes, double* d, double* c, double* r,
+                                         int* pivots, void* hip_stream) {
+    if (!work) return SP_ERR_INVALID_ARG;
+    const int st = ge_check(n_lambda, m_theta, f, steps, alpha, tol, work, work_bytes, d, c, r, pivots);
+    if (st != SP_OK) return st;
+    return ge_run(n_lambda, m_theta, f, steps, alpha, tol, work, d, c, r, pivots, (hipStream_t)hip_stream);
+}
+
+extern "C" int sphere_poisson_ge_lowrank_static(int n_lambda, int m_theta, const double* f, int steps, double alpha,
+                                                double tol, double* d, double* c, double* r, int* pivots,
+                                                void* hip_stream) {
+    const int st = ge_check(n_lambda, m_theta, f, steps, alpha, tol, nullptr, 0, d, c, r, pivots);
+    if (st != SP_OK) return st;
+    if (ge_layout(n_lambda, m_theta).total > kGeStaticBytes) return SP_ERR_UNSUPPORTED_SIZE;
+    void* work = nullptr;
+    const int sa = scratch_address(&work);
+    if (sa != SP_OK) return sa;
+    return ge_run(n_lambda, m_theta, f, steps, alpha, tol, work, d, c, r, pivots, (hipStream_t)hip_stream);
 }
