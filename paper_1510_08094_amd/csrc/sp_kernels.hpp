@@ -570,14 +570,18 @@ template <> __device__ __forceinline__ Cx<double> vfrom_real<Cx<double>>(double 
 
 // Partitioned solve of both parity classes for k != 0 (or the transposed
 // systems).  Each thread owns a contiguous chunk of rows of one class: its
-// first row is a separator, the others are interior rows.  For the interior
-// rows the thread keeps only their right-hand sides and the reciprocal pivots
-// of a top-down elimination.  That elimination gives the last interior row as
-// an affine function of the chunk's separator S and the next separator S+; a
-// bottom-up elimination gives the first interior row the same way.  The
-// separators then form a tridiagonal system, solved by parallel cyclic
-// reduction, and a final forward/backward substitution with S and S+ known
-// rebuilds the interior rows.
+// first row is a separator, the others are interior rows.  A top-down
+// elimination over the interior rows, with the chunk's separator S and the
+// next separator S+ unknown, writes each interior row as
+//   x_ii = dy_ii - S dv_ii - cp_ii x_{ii+1},
+// which at the last interior row is an affine function of S and S+.
+// Substituting these relations into one another from the top gives the first
+// interior row the same way, in the same pass (a running product of the -cp).
+// The separators then form a tridiagonal system, solved by parallel cyclic
+// reduction, and one backward pass with S and S+ known rebuilds the interior
+// rows: from the kept dy, dv and cp where they fit in registers (SPIKE is
+// true), else by a forward and a backward substitution that recompute the
+// band from the row index and keep only dy and the reciprocal pivots.
 
 // Right-hand-side slot of row ii of a thread's chunk in the "solve order"
 // used for values kept between kernels: class A rows first, then class B,
@@ -586,6 +590,13 @@ template <> __device__ __forceinline__ Cx<double> vfrom_real<Cx<double>>(double 
 // s p < nc + s <= nc + SMAX slots, so with SMAX <= 31 the slots of a line (both
 // classes) stay below m + 64.
 __host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64; }
+
+// Whether a solve of SMAX-row chunks with right-hand sides of type V in
+// precision T keeps the top-down multipliers and separator weights of every
+// row: two more register arrays, at most 256 bytes per thread for all three
+// (real and complex float; not double, whose chunks would spill).
+template <typename T, typename V, int SMAX>
+__host__ __device__ constexpr bool solve_keeps_spike() { return (int)(sizeof(V) + 2 * sizeof(T)) * SMAX <= 256; }
 
 // load(p, q, slot, own) returns the right-hand side of the row of coefficient
 // q (line position p: q for cosine, m - q for sine; solve-order slot); own is
@@ -596,6 +607,7 @@ __host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64
 template <typename T, typename V, int SMAX, typename Load, typename Store>
 __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
                                                      int m, int k, bool sine, bool transposed, int tid) {
+    constexpr bool SPIKE = solve_keeps_spike<T, V, SMAX>();
     const int qhi = sine ? m : m - 1;
     const ClassInfo A = make_class<SMAX>(sine ? 2 : 0, qhi);
     const ClassInfo B = make_class<SMAX>(1, qhi);
@@ -615,8 +627,10 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
         band_kk<T>((T)(C.q0 + 2 * row), kk, first, row == C.nc - 1, transposed, a, b, c);
     };
 
-    V r[SMAX];
-    T iv[SMAX];
+    V r[SMAX];                   // right-hand sides (SPIKE: then dy)
+    T cp[SPIKE ? SMAX : 1];      // SPIKE: cp and dv of every interior row
+    T dv[SPIKE ? SMAX : 1];
+    T iv[SPIKE ? 1 : SMAX];      // otherwise: the reciprocal pivots
     const int slot0 = (inA ? 0 : A.s * A.p) + p;
     // Branch-free, so that every load of the chunk is issued before the first
     // use: rows past the chunk re-read the chunk's first row, and idle threads
@@ -631,48 +645,32 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     }
     lds_barrier();   // B1: the line may now be overwritten by scratch
 
-    // top-down: x_ii = dy - S dv - cp x_{ii+1}; at the last interior row
-    // x = yL - S vL - S+ wL
-    V yL{};
-    T vL = (T)-1, wL = (T)0;   // no interior row: the "last interior row" is the separator
+    // Top-down.  Last interior row: x = yL - S vL - S+ wL (with no interior
+    // row the "last interior row" is the separator: yL = 0, vL = -1, wL = 0).
+    // First interior row, composed along the way: x_1 = yF + S gv + x_{ii+1} g,
+    // with g the product of the -cp so far; at the end x_1 = yF - S vF - S+ wF
+    // (with no interior row it is the next separator: yF = 0, vF = 0, wF = -1).
+    V yL{}, yF{};
+    T vL = (T)-1, wL = (T)0, vF = (T)0, wF = (T)-1;
     {
-        T cp = 0, dv = 0;
-        V dy{};
+        T g = (T)1, gv = (T)0;
 #pragma unroll
         for (int ii = 1; ii < SMAX; ++ii) {
             if (ii <= ni) {
                 const int row = lo + ii;
                 T a, b, c;
                 rowband(row, false, a, b, c);
-                const T inv = rcp_pivot(b - a * cp);
-                iv[ii] = inv;
-                cp = c * inv;
-                dy = (r[ii] - dy * a) * inv;
-                dv = (ii == 1 ? a : -a * dv) * inv;
+                const T inv = rcp_pivot(b - a * wL);
+                wL = c * inv;
+                yL = (r[ii] - yL * a) * inv;
+                vL = -a * vL * inv;
+                if constexpr (SPIKE) { r[ii] = yL; cp[ii] = wL; dv[ii] = vL; } else { iv[ii] = inv; }
+                yF = yF + yL * g;
+                gv = gv - vL * g;
+                g = -wL * g;
             }
         }
-        if (ni >= 1) { yL = dy; vL = dv; wL = cp; }
-    }
-    // bottom-up: x_ii = ey - cq x_{ii-1} - ew S+; at the first interior row
-    // x = yF - S vF - S+ wF
-    V yF{};
-    T vF = (T)0, wF = (T)-1;   // no interior row: the "first interior row" is the next separator
-    {
-        T cq = 0, ew = 0;
-        V ey{};
-#pragma unroll
-        for (int ii = SMAX - 1; ii >= 1; --ii) {
-            if (ii <= ni) {
-                const int row = lo + ii;
-                T a, b, c;
-                rowband(row, false, a, b, c);
-                const T inv = rcp_pivot(b - c * cq);
-                cq = a * inv;
-                ey = (r[ii] - ey * c) * inv;
-                ew = (ii == ni ? c : -c * ew) * inv;
-            }
-        }
-        if (ni >= 1) { yF = ey; vF = cq; wF = ew; }
+        if (ni >= 1) { vF = -gv; wF = -g; }
     }
     // scratch: de[ptot] (V), al[ptot], be[ptot], ga[ptot] (T)
     V* de = reinterpret_cast<V*>(scratch);
@@ -734,28 +732,41 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     lds_barrier();   // scratch no longer needed: write the solution
     if (cnt > 0) {
         store(lpos(C.q0 + 2 * lo), S);
-        // interior rows with both separators known: forward, then backward substitution
-        V prev = S;
+        if constexpr (SPIKE) {
+            V next = Sn;
 #pragma unroll
-        for (int ii = 1; ii < SMAX; ++ii) {
-            if (ii <= ni) {
-                const int row = lo + ii;
-                T a, b, c;
-                rowband(row, false, a, b, c);
-                r[ii] = (r[ii] - prev * a) * iv[ii];
-                prev = r[ii];
+            for (int ii = SMAX - 1; ii >= 1; --ii) {
+                if (ii <= ni) {
+                    r[ii] = r[ii] - S * dv[ii] - next * cp[ii];
+                    next = r[ii];
+                    store(lpos(C.q0 + 2 * (lo + ii)), r[ii]);
+                }
             }
-        }
-        V next = Sn;
+        } else {
+            // r still holds the right-hand sides: a forward substitution
+            // from x_0 = S, then a backward one from S+
+            V prev = S;
 #pragma unroll
-        for (int ii = SMAX - 1; ii >= 1; --ii) {
-            if (ii <= ni) {
-                const int row = lo + ii;
-                T a, b, c;
-                rowband(row, false, a, b, c);
-                r[ii] = r[ii] - next * (c * iv[ii]);
-                next = r[ii];
-                store(lpos(C.q0 + 2 * row), r[ii]);
+            for (int ii = 1; ii < SMAX; ++ii) {
+                if (ii <= ni) {
+                    const int row = lo + ii;
+                    T a, b, c;
+                    rowband(row, false, a, b, c);
+                    r[ii] = (r[ii] - prev * a) * iv[ii];
+                    prev = r[ii];
+                }
+            }
+            V next = Sn;
+#pragma unroll
+            for (int ii = SMAX - 1; ii >= 1; --ii) {
+                if (ii <= ni) {
+                    const int row = lo + ii;
+                    T a, b, c;
+                    rowband(row, false, a, b, c);
+                    r[ii] = r[ii] - next * (c * iv[ii]);
+                    next = r[ii];
+                    store(lpos(C.q0 + 2 * row), r[ii]);
+                }
             }
         }
     }
