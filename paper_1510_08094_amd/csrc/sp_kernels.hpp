@@ -581,12 +581,43 @@ template <> __device__ __forceinline__ Cx<double> vfrom_real<Cx<double>>(double 
 // reduction, and one backward pass with S and S+ known rebuilds the interior
 // rows: from the kept dy, dv and cp where they fit in registers (SPIKE is
 // true), else by a forward and a backward substitution that recompute the
-// band from the row index and keep only dy and the reciprocal pivots.
+// band from the row index and keep only the right-hand sides and the
+// reciprocal pivots.
+//
+// Every chunk of both classes has the same length s, so the row loops run a
+// count that is the same for the whole workgroup.  The last chunk of a class
+// is filled up with padding rows that continue the band past the class's last
+// row.  That row's superdiagonal is zero, so the coupling runs from the real
+// rows into the padding only: the real rows' elimination, their separator
+// equations and their solution are those of the class alone, and the padding
+// rows' values are finite and never stored.
+
+// Rows per chunk (both classes) and chunks per class for classes of ncA and
+// ncB rows and chunks of at most smax rows; the same on the host (thread
+// counts, LDS sizes) and in the kernels.  The length is odd when possible:
+// the rows of a class sit two line positions apart, so consecutive chunks
+// start 2s positions apart, and an odd s spreads the threads' LDS accesses
+// over the banks (at most two-way conflicts instead of up to 16-way).
+struct SolveChunks {
+    int s, pA, pB;
+};
+__host__ __device__ constexpr SolveChunks solve_chunks(int ncA, int ncB, int smax) {
+    const int nc = ncA > ncB ? ncA : ncB;
+    const int p = (nc + smax - 1) / smax;
+    int s = p ? (nc + p - 1) / p : 0;
+    if ((s & 1) == 0 && s < smax) s += 1;
+    SolveChunks c{s, s ? (ncA + s - 1) / s : 0, s ? (ncB + s - 1) / s : 0};
+    return c;
+}
+
+// Rows of the two classes of a k != 0 system: class A holds the even q from
+// 0 (cosine) or 2 (sine), class B the odd q, up to m - 1 (cosine) or m (sine).
+__host__ __device__ constexpr int class_rows(int q0, int qhi) { return qhi >= q0 ? (qhi - q0) / 2 + 1 : 0; }
 
 // Right-hand-side slot of row ii of a thread's chunk in the "solve order"
 // used for values kept between kernels: class A rows first, then class B,
 // each interleaved over the chunks (consecutive threads, consecutive slots).
-// A class of nc rows in p chunks of s rows (no chunk empty) uses
+// A class of nc rows in p chunks of s rows (padding included) uses
 // s p < nc + s <= nc + SMAX slots, so with SMAX <= 31 the slots of a line (both
 // classes) stay below m + 64.
 __host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64; }
@@ -598,19 +629,36 @@ __host__ __device__ __forceinline__ int solve_slot_stride(int m) { return m + 64
 template <typename T, typename V, int SMAX>
 __host__ __device__ constexpr bool solve_keeps_spike() { return (int)(sizeof(V) + 2 * sizeof(T)) * SMAX <= 256; }
 
-// load(p, q, slot, own) returns the right-hand side of the row of coefficient
-// q (line position p: q for cosine, m - q for sine; solve-order slot); own is
-// false for the repeated loads that keep the loads branch-free (a row past
-// the chunk, or an idle thread), which must not be counted twice by a load
-// that accumulates; store(p, x) receives the solution.  Every load happens before the first
-// barrier and every store after the last use of the LDS scratch.
-template <typename T, typename V, int SMAX, typename Load, typename Store>
-__device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store, unsigned char* __restrict__ scratch,
-                                                     int m, int k, bool sine, bool transposed, int tid) {
+// fetch(slot) issues a row's global reads and returns them (NoFetch when a
+// load reads only the LDS line); load(p, q, slot, own, fetched) returns the
+// right-hand side of the row of coefficient
+// q at line position p (q for cosine, m - q for sine) with solve-order slot
+// `slot`.  For a padding row q lies past the class, p is clamped into the
+// line (a valid position whose value is only a placeholder) and own is
+// false, so a load that accumulates over the rows skips it; a load that also
+// keeps its value writes the padding row's own slot.  store(p, x) receives
+// the solution of the real rows (PAD: also the padding rows', at positions
+// in the line's margins).  Every load happens before the first barrier and
+// every store after the last use of the LDS scratch.
+struct NoFetch {};
+
+template <typename T, typename V, int SMAX, bool PAD = false, bool FULL = false, typename Fetch, typename Load,
+          typename Store>
+__device__ __forceinline__ void solve_partitioned_io(Fetch&& fetch, Load&& load, Store&& store,
+                                                     unsigned char* __restrict__ scratch, int m, int k, bool sine,
+                                                     bool transposed, int tid) {
     constexpr bool SPIKE = solve_keeps_spike<T, V, SMAX>();
     const int qhi = sine ? m : m - 1;
-    const ClassInfo A = make_class<SMAX>(sine ? 2 : 0, qhi);
-    const ClassInfo B = make_class<SMAX>(1, qhi);
+    ClassInfo A, B;
+    A.q0 = sine ? 2 : 0;
+    B.q0 = 1;
+    A.nc = class_rows(A.q0, qhi);
+    B.nc = class_rows(1, qhi);
+    const SolveChunks ch = solve_chunks(A.nc, B.nc, SMAX);
+    const int s = FULL ? SMAX : ch.s;            // rows per chunk, the same in every thread
+    A.s = B.s = s;
+    A.p = ch.pA;
+    B.p = ch.pB;
     const int ptot = A.p + B.p;
     const bool inA = tid < A.p;
     const bool inB = !inA && tid < ptot;
@@ -618,30 +666,56 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     const int p = inA ? tid : tid - A.p;
     const int cls_lo = inA ? 0 : A.p;            // reduced-row range of this class
     const int cls_hi = inA ? A.p : ptot;
-    const int lo = p * C.s;
-    const int cnt = (inA || inB) ? min(C.s, C.nc - lo) : 0;
-    const int ni = cnt - 1;
-    auto lpos = [&](int q) { return sine ? m - q : q; };
+    const int lo = p * s;
+    const int cnt = (inA || inB) ? min(s, C.nc - lo) : 0;   // real rows of the chunk; the rest are padding
+    // row ii of the chunk: coefficient Q0 + 2 ii at line position P0 + ii dP, solve-order slot slot0 + ii C.p
+    const int Q0 = C.q0 + 2 * lo;
+    const int P0 = sine ? m - Q0 : Q0;
+    const int dP = sine ? -2 : 2;
+    const int slot0 = (inA ? 0 : s * A.p) + p;
+    const int ilast = C.nc - 1 - lo;             // the class's last row as a chunk index
     const T kk = (T)k * (T)k;
-    auto rowband = [&](int row, bool first, T& a, T& b, T& c) {
-        band_kk<T>((T)(C.q0 + 2 * row), kk, first, row == C.nc - 1, transposed, a, b, c);
+    const T qT0 = (T)Q0;
+    // q is carried as a running value (exact: q < 2^24) rather than converted per row
+    auto rowband = [&](T qrow, int ii, bool first, T& a, T& b, T& c) {
+        band_kk<T>(qrow, kk, first, ii == ilast, transposed, a, b, c);
     };
 
     V r[SMAX];                   // right-hand sides (SPIKE: then dy)
     T cp[SPIKE ? SMAX : 1];      // SPIKE: cp and dv of every interior row
     T dv[SPIKE ? SMAX : 1];
     T iv[SPIKE ? 1 : SMAX];      // otherwise: the reciprocal pivots
-    const int slot0 = (inA ? 0 : A.s * A.p) + p;
-    // Branch-free, so that every load of the chunk is issued before the first
-    // use: rows past the chunk re-read the chunk's first row, and idle threads
-    // (always of class B) re-read the first row of class B, with that row's
-    // own slot, so a load that also stores writes the owner's value again.
+    // Branch-free within a thread: every row's global reads (fetch) are
+    // issued before any row is formed (a branch per row, or a fetch next to
+    // its use, waits on each row's reads in turn).  Padding rows, and rows at
+    // or past s (which exist only when s < SMAX), re-read the chunk's first
+    // row, with its slot (a load that also keeps its value writes the same
+    // value again): their right-hand sides only need to be finite.
+    // (The selects pick between the row's own value, linear in ii, and the
+    // first row's, so no per-row multiply is needed; q is only used with the
+    // row's position, so a padding row keeps its own.)  PAD: the line has
+    // margins the padding rows may read and write (at least 2 SMAX + 2
+    // entries on each side, the loads' values there finite), so a padding row
+    // uses its own position and slot and rows need no selects; rows at or
+    // past s still re-read the first row (a test of s, the same in every
+    // thread).
+    using PF = decltype(fetch(0u));
+    if (cnt > 0) {
+        PF pf[SMAX];
 #pragma unroll
-    for (int ii = 0; ii < SMAX; ++ii) {
-        const int iic = ii < cnt ? ii : 0;
-        const int row = cnt > 0 ? lo + iic : 0;
-        const int q = C.q0 + 2 * row;
-        r[ii] = load(lpos(q), q, cnt > 0 ? slot0 + iic * C.p : A.s * A.p, ii < cnt);
+        for (int ii = 0; ii < SMAX; ++ii) {
+            const int iu = ii < s ? ii : 0;
+            const int sl = PAD ? slot0 + iu * C.p : (ii < cnt ? slot0 + ii * C.p : slot0);
+            pf[ii] = fetch((unsigned)sl);
+        }
+#pragma unroll
+        for (int ii = 0; ii < SMAX; ++ii) {
+            const int iu = ii < s ? ii : 0;
+            const bool own = ii < cnt;
+            const int sl = PAD ? slot0 + iu * C.p : (own ? slot0 + ii * C.p : slot0);
+            const int pos = PAD ? P0 + iu * dP : (own ? P0 + ii * dP : P0);
+            r[ii] = load(pos, Q0 + 2 * ii, (unsigned)sl, own, pf[ii]);
+        }
     }
     lds_barrier();   // B1: the line may now be overwritten by scratch
 
@@ -650,16 +724,18 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     // First interior row, composed along the way: x_1 = yF + S gv + x_{ii+1} g,
     // with g the product of the -cp so far; at the end x_1 = yF - S vF - S+ wF
     // (with no interior row it is the next separator: yF = 0, vF = 0, wF = -1).
+    // FULL (the caller guarantees s == SMAX): no row tests.  (A second copy of
+    // the loops for s == SMAX beside the tested ones made the kernels spill.)
     V yL{}, yF{};
     T vL = (T)-1, wL = (T)0, vF = (T)0, wF = (T)-1;
-    {
-        T g = (T)1, gv = (T)0;
+    if (cnt > 0) {
+        T g = (T)1, gv = (T)0, qrow = qT0;
 #pragma unroll
         for (int ii = 1; ii < SMAX; ++ii) {
-            if (ii <= ni) {
-                const int row = lo + ii;
+            if (FULL || ii < s) {
+                qrow += (T)2;
                 T a, b, c;
-                rowband(row, false, a, b, c);
+                rowband(qrow, ii, false, a, b, c);
                 const T inv = rcp_pivot(b - a * wL);
                 wL = c * inv;
                 yL = (r[ii] - yL * a) * inv;
@@ -670,7 +746,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
                 g = -wL * g;
             }
         }
-        if (ni >= 1) { vF = -gv; wF = -g; }
+        if (FULL || s > 1) { vF = -gv; wF = -g; }
     }
     // scratch: de[ptot] (V), al[ptot], be[ptot], ga[ptot] (T)
     V* de = reinterpret_cast<V*>(scratch);
@@ -683,7 +759,7 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     V nde{};
     if (cnt > 0) {
         T a0, b0, c0;
-        rowband(lo, lo == 0, a0, b0, c0);
+        rowband(qT0, 0, lo == 0, a0, b0, c0);
         V pyL{};
         T pvL = 0, pwL = 0;
         if (p > 0) { pyL = de[tid - 1]; pvL = al[tid - 1]; pwL = ga[tid - 1]; }
@@ -731,41 +807,43 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
     if (cnt > 0 && tid + 1 < cls_hi) Sn = de[tid + 1];
     lds_barrier();   // scratch no longer needed: write the solution
     if (cnt > 0) {
-        store(lpos(C.q0 + 2 * lo), S);
+        store(P0, S);
         if constexpr (SPIKE) {
             V next = Sn;
 #pragma unroll
             for (int ii = SMAX - 1; ii >= 1; --ii) {
-                if (ii <= ni) {
+                if (FULL || ii < s) {
                     r[ii] = r[ii] - S * dv[ii] - next * cp[ii];
                     next = r[ii];
-                    store(lpos(C.q0 + 2 * (lo + ii)), r[ii]);
+                    if (PAD || ii < cnt) store(P0 + ii * dP, r[ii]);
                 }
             }
         } else {
             // r still holds the right-hand sides: a forward substitution
             // from x_0 = S, then a backward one from S+
             V prev = S;
+            T qrow = qT0;
 #pragma unroll
             for (int ii = 1; ii < SMAX; ++ii) {
-                if (ii <= ni) {
-                    const int row = lo + ii;
+                if (FULL || ii < s) {
+                    qrow += (T)2;
                     T a, b, c;
-                    rowband(row, false, a, b, c);
+                    rowband(qrow, ii, false, a, b, c);
                     r[ii] = (r[ii] - prev * a) * iv[ii];
                     prev = r[ii];
                 }
             }
             V next = Sn;
+            qrow += (T)2;
 #pragma unroll
             for (int ii = SMAX - 1; ii >= 1; --ii) {
-                if (ii <= ni) {
-                    const int row = lo + ii;
+                if (FULL || ii < s) {
+                    qrow -= (T)2;
                     T a, b, c;
-                    rowband(row, false, a, b, c);
+                    rowband(qrow, ii, false, a, b, c);
                     r[ii] = r[ii] - next * (c * iv[ii]);
                     next = r[ii];
-                    store(lpos(C.q0 + 2 * row), r[ii]);
+                    if (PAD || ii < cnt) store(P0 + ii * dP, r[ii]);
                 }
             }
         }
@@ -776,7 +854,8 @@ __device__ __forceinline__ void solve_partitioned_io(Load&& load, Store&& store,
 template <typename T, int SMAX, typename V>
 __device__ __forceinline__ void solve_partitioned(V* __restrict__ buf, unsigned char* __restrict__ scratch,
                                                   int m, int k, bool sine, bool transposed, int tid) {
-    solve_partitioned_io<T, V, SMAX>([&](int p, int, int, bool) { return buf[p]; },
+    solve_partitioned_io<T, V, SMAX>([](unsigned) { return NoFetch{}; },
+                                     [&](int p, int, unsigned, bool, NoFetch) { return buf[p]; },
                                      [&](int p, V x) { buf[p] = x; }, scratch, m, k, sine, transposed, tid);
 }
 
@@ -1331,18 +1410,22 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
         // correction); correction, r = F - (L - k^2) X in float64 from the
         // analysed iterate X in LDS.  The solution goes straight to the
         // float32 column used by the synthesis.
-        auto load = [&](int p, int q, int slot, bool own) -> Cx<double> {
+        // The neighbours are read unconditionally (positions clamped into the
+        // line; a missing neighbour's band entry is zero), so the reads of a
+        // row do not wait on one another.
+        // correction: F of the row, read from HBM ahead of the rows' LDS work
+        auto fetch = [&](unsigned slot) -> Cx<double> { return RESID ? Fk[slot] : Cx<double>{}; };
+        auto load = [&](int p, int q, unsigned slot, bool own, Cx<double> f) -> Cx<double> {
             if (!RESID) {
-                const Cx<double> f = bufd[p];
+                f = bufd[p];
                 Fk[slot] = f;
                 return f;
             }
             double sub, diag, sup;
             band<double>(q, k, q - 2 < qlo, q + 2 > qhi, TRANS, sub, diag, sup);
-            Cx<double> ax = bufd[p] * diag;
-            if (q - 2 >= qlo) ax = ax + bufd[sine ? p + 2 : p - 2] * sub;
-            if (q + 2 <= qhi) ax = ax + bufd[sine ? p - 2 : p + 2] * sup;
-            const Cx<double> f = Fk[slot], r = f - ax;
+            const Cx<double> ylo = bufd[max(p - 2, 0)], yhi = bufd[min(p + 2, m - 1)];
+            const Cx<double> ax = bufd[p] * diag + ylo * (sine ? sup : sub) + yhi * (sine ? sub : sup);
+            const Cx<double> r = f - ax;
             if (want_norm && own) {
                 acc_r += r.x * r.x + r.y * r.y;
                 acc_f += f.x * f.x + f.y * f.y;
@@ -1351,12 +1434,13 @@ __device__ __forceinline__ void theta_mixed_body(const ThetaMixArgs& a, int k, u
         };
         if (k < a.k64) {   // ill-conditioned low wavenumbers: float64 elimination
             solve_partitioned_io<double, Cx<double>, SMAXD>(
-                load, [&](int p, Cx<double> x) { buff[p] = Cx<float>{(float)x.x, (float)x.y}; }, smem_raw, m, k,
-                sine, TRANS, tid);
+                fetch, load, [&](int p, Cx<double> x) { buff[p] = Cx<float>{(float)x.x, (float)x.y}; }, smem_raw, m,
+                k, sine, TRANS, tid);
         } else {
             solve_partitioned_io<float, Cx<float>, SMAXF>(
-                [&](int p, int q, int slot, bool own) {
-                    const Cx<double> r = load(p, q, slot, own);
+                fetch,
+                [&](int p, int q, unsigned slot, bool own, Cx<double> f) {
+                    const Cx<double> r = load(p, q, slot, own, f);
                     return Cx<float>{(float)r.x, (float)r.y};
                 },
                 [&](int p, Cx<float> x) { buff[p] = x; }, smem_raw, m, k, sine, TRANS, tid);

@@ -25,6 +25,14 @@
 namespace sp {
 
 constexpr int kRealPairHold = 8;    // coefficient pairs per thread in the split steps
+// LDS before and after the line of a real-part pass: 64 float64 entries on
+// each side, zero on the solve's loads.  A row's residual reads both band
+// neighbours without testing for the ends of the line, and the padding rows
+// of a class's last chunk (at most 2 SMAX + 2 entries past the line, SMAX <=
+// 31) read, and write their solution, in the margins.
+constexpr int kRealLineMarginEntries = 64;
+constexpr int kRealLineMargin = kRealLineMarginEntries * 8;
+
 constexpr int kRealLoadHold = 24;   // line values per thread (at least m / threads) in the k = 0 steps
 
 // Threads of a real-part workgroup must cover the split pairs and the loads.
@@ -279,10 +287,11 @@ __device__ __forceinline__ void theta_mixed_real_k0(const ThetaMixArgs& a, int p
 template <int EPT, int RMAX, int SMAXF, int SMAXD, bool RESID, bool TRANS, bool NORM = false>
 __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int k, int part,
                                                       unsigned char* smem_raw, Cx<double>* red) {
-    double* yd = reinterpret_cast<double*>(smem_raw);
-    Cx<double>* zd = reinterpret_cast<Cx<double>*>(smem_raw);
-    float* yf = reinterpret_cast<float*>(smem_raw);
-    Cx<float>* zf = reinterpret_cast<Cx<float>*>(smem_raw);
+    unsigned char* line = smem_raw + kRealLineMargin;
+    double* yd = reinterpret_cast<double*>(line);
+    Cx<double>* zd = reinterpret_cast<Cx<double>*>(line);
+    float* yf = reinterpret_cast<float*>(line);
+    Cx<float>* zf = reinterpret_cast<Cx<float>*>(line);
     const int m = a.m, N = a.N;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool sine = (k & 1) != 0;
@@ -293,30 +302,55 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
         const double s = block_sum(fpart, red);
         if (tid == 0) *a.fint_out = s;
     }
+    static_assert(2 * SMAXF + 2 <= kRealLineMarginEntries && 2 * SMAXD + 2 <= kRealLineMarginEntries,
+                  "the solve's padding rows must stay in the line's margins");
+    // The kernels built for the length-5000 transform run m = 10^4 only (the
+    // plan checks it): both classes have 5000 rows and every chunk is full.
+    constexpr bool FULL = RMAX == kRadixFixed5000;
+    static_assert(!FULL || (solve_chunks(5000, 5000, SMAXF).s == SMAXF && solve_chunks(5000, 5000, SMAXD).s == SMAXD),
+                  "full chunks at m = 10^4");
+    if (tid < kRealLineMarginEntries) {   // the zero margins (the LDS may hold another pass's data)
+        yd[tid - kRealLineMarginEntries] = 0.0;
+        yd[m + tid] = 0.0;
+    }
     __syncthreads();
     fft_lds<double, false, EPT, RMAX>(zd, 0, a.fft, a.tw64, tid, a.nthr_fft, tid < a.nthr_fft);
     const double invm = 1.0 / (double)m;
     rdct_split_forward<double>(zd, a.eq64, a.ws64, m, TRANS ? 1.0 : invm, TRANS ? 1.0 : 2.0 * invm, tid, nthr);
 
-    const int qlo = sine ? 1 : 0, qhi = sine ? m : m - 1;
     double* Fk = reinterpret_cast<double*>(a.fco) + (size_t)(2 * k + part) * solve_slot_stride(m);
     // NORM (correction pass only): the residual sums for the info, in a build of its own so
     // that the plain pass carries no extra registers
     constexpr bool want_norm = RESID && NORM;
     double acc_r = 0.0, acc_f = 0.0;
     if (k != 0) {
-        auto load = [&](int p, int q, int slot, bool own) -> double {
+        // Row q of (L - k^2) X: diag X_q + sub X_{q-2} + sup X_{q+2}, with
+        // sub = base - lin and sup = base + lin.  X_{q-2} sits at position
+        // p - 2 for a cosine line and p + 2 for a sine line, so the weight of
+        // position p - 2 is base - sigma lin with sigma = -1 for sine.  A
+        // neighbour past either end of the class reads a margin zero.
+        const double kkd = (double)k * (double)k;
+        const double lin_w = (sine ? -1.0 : 1.0) * (TRANS ? 0.25 : 0.75);
+        const double base_c = TRANS ? 0.0 : 0.5;
+        // F of the row in solve order, at a 32-bit byte offset from the
+        // wavenumber's (uniform) base; the correction reads it from HBM ahead of
+        // the rows' LDS work
+        auto fslot = [&](unsigned slot) { return reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(Fk) + slot * 8u); };
+        auto fetch = [&](unsigned slot) -> double { return RESID ? *fslot(slot) : 0.0; };
+        auto load = [&](int p, int q, unsigned slot, bool own, double f) -> double {
             if (!RESID) {
-                const double f = yd[p];
-                Fk[slot] = f;
+                f = yd[p];
+                *fslot(slot) = f;
                 return f;
             }
-            double sub, diag, sup;
-            band<double>(q, k, q - 2 < qlo, q + 2 > qhi, TRANS, sub, diag, sup);
+            const double qd = (double)q, qq = qd * qd;
+            const double base = __builtin_fma(qq, 0.25, base_c);
+            const double lin = qd * lin_w;
+            const double diag = __builtin_fma(qq, -0.5, -kkd);
             double ax = yd[p] * diag;
-            if (q - 2 >= qlo) ax += yd[sine ? p + 2 : p - 2] * sub;
-            if (q + 2 <= qhi) ax += yd[sine ? p - 2 : p + 2] * sup;
-            const double f = Fk[slot], r = f - ax;
+            ax = __builtin_fma(yd[p - 2], base - lin, ax);
+            ax = __builtin_fma(yd[p + 2], base + lin, ax);
+            const double r = f - ax;
             if (want_norm && own) {
                 acc_r += r * r;
                 acc_f += f * f;
@@ -324,11 +358,11 @@ __device__ __forceinline__ void theta_mixed_real_body(const ThetaMixArgs& a, int
             return r;
         };
         if (k < a.k64) {
-            solve_partitioned_io<double, double, SMAXD>(
-                load, [&](int p, double x) { yf[p] = (float)x; }, smem_raw, m, k, sine, TRANS, tid);
+            solve_partitioned_io<double, double, SMAXD, true, FULL>(
+                fetch, load, [&](int p, double x) { yf[p] = (float)x; }, smem_raw, m, k, sine, TRANS, tid);
         } else {
-            solve_partitioned_io<float, float, SMAXF>(
-                [&](int p, int q, int slot, bool own) { return (float)load(p, q, slot, own); },
+            solve_partitioned_io<float, float, SMAXF, true, FULL>(
+                fetch, [&](int p, int q, unsigned slot, bool own, double f) { return (float)load(p, q, slot, own, f); },
                 [&](int p, float x) { yf[p] = x; }, smem_raw, m, k, sine, TRANS, tid);
         }
         lds_barrier();

@@ -176,15 +176,17 @@ ClassCounts classes(int m, bool sine, bool k0) {
     return c;
 }
 
+// Threads a solve needs: the chunks of both classes for k != 0 (one chunk
+// length for both, as the kernels lay them out) and for the k = 0 system.
 int solve_threads(int m, int smax) {
     int best = 0;
-    for (int s = 0; s < 2; ++s)
-        for (int z = 0; z < 2; ++z) {
-            if (s && z) continue;
-            ClassCounts c = classes(m, s, z);
-            best = std::max(best, ceil_div(c.ncA, smax) + ceil_div(c.ncB, smax));
-        }
-    return best;
+    for (int s = 0; s < 2; ++s) {
+        const ClassCounts c = classes(m, s, false);
+        const sp::SolveChunks ch = sp::solve_chunks(c.ncA, c.ncB, smax);
+        best = std::max(best, ch.pA + ch.pB);
+    }
+    const ClassCounts z = classes(m, false, true);
+    return std::max(best, ceil_div(z.ncA, smax) + ceil_div(z.ncB, smax));
 }
 
 
@@ -432,10 +434,11 @@ void set_lds_attr(const KernelSet<T>& ks, size_t lam, size_t theta) {
     (void)hipGetLastError();
 }
 
-// LDS of the real-part theta pass: the float64 line (m reals) or the solve
-// scratch (separator rows; k = 0 scan values), whichever is larger.
+// LDS of the real-part theta pass: the float64 line (m reals, with its zero
+// margins) or the solve scratch (separator rows; k = 0 scan values),
+// whichever is larger.
 size_t real_theta_lds_bytes(int m, int ptot) {
-    size_t a = (size_t)m * sizeof(double);
+    size_t a = (size_t)m * sizeof(double) + 2 * sp::kRealLineMargin;
     size_t b = (size_t)ptot * 4 * sizeof(double);
     size_t c = (size_t)ptot * 2 * sizeof(double);
     return (std::max(a, std::max(b, c)) + 15) & ~(size_t)15;
@@ -590,6 +593,12 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
     // lambda and theta kernels are picked separately: either may run a fixed transform
     const int rs_lam = radix_set(p->fft_lam, p->lam_threads, true);
     const int rs_th = radix_set(p->fft_theta, p->theta_fft_threads, p->theta_real);
+    // the fixed real-part kernels assume m = 2 * 5000 (full solve chunks); the
+    // fixed transform is only chosen for a real-part line of that length
+    if (rs_th == sp::kRadixFixed5000 && m != 2 * 5000) {
+        delete p;
+        return SP_ERR_UNSUPPORTED_SIZE;
+    }
     {
         const KernelSet<double> L = pick_kernels<double>(rs_lam), T = pick_kernels<double>(rs_th);
         p->kd = KernelSet<double>{L.fwd, L.inv, T.theta, T.theta_real};
