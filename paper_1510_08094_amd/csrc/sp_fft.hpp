@@ -415,10 +415,12 @@ __device__ __forceinline__ void fft_ct_passes(Cx<T>* __restrict__ buf, const Cx<
 // count match.
 enum FixedFft { kFixedNone = 0, kFixed5000 = 1 };
 constexpr int kRadixFixed5000 = -5000;
-// 5000 = 5 10^3: a radix-5 pass (two butterflies per thread), then three
-// radix-10 passes with one butterfly per thread
+// 5000 = 10 5 10 10: radix-10 passes with one butterfly per thread and a
+// radix-5 pass with two.  The radix-5 pass comes second: placed there, every
+// pass's LDS writes hit distinct banks, where after a first radix-5 pass the
+// radix-10 writes of span 5 collide two to three ways in float64.
 constexpr int kFixed5000Threads = 500;
-constexpr int kFixed5000Radices[4] = {5, 10, 10, 10};
+constexpr int kFixed5000Radices[4] = {10, 5, 10, 10};
 
 // Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
 // radices compiled into this instantiation.
@@ -429,7 +431,7 @@ __device__ __forceinline__ void fft_lds(Cx<T>* __restrict__ base, int off, const
     if constexpr (RMAX == kRadixFixed5000) {
         (void)d;
         (void)nthr;
-        fft_ct_passes<T, INV, 5000, kFixed5000Threads, 1, 5, 10, 10, 10>(base + off, ptw, t0, active);
+        fft_ct_passes<T, INV, 5000, kFixed5000Threads, 1, 10, 5, 10, 10>(base + off, ptw, t0, active);
     } else {
         int Ns = 1;
         for (int p = 0; p < d.npass; ++p) {

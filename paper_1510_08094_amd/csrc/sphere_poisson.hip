@@ -90,7 +90,7 @@ void cis_neg(long long t, long long N, double* re, double* im) {
 }
 
 // ------------------------------------------------------------ FFT planning
-// The compiled-in transform of length 5000 (radices 5, 10, 10, 10): its
+// The compiled-in transform of length 5000 (radices 10, 5, 10, 10): its
 // radix-10 passes exist only in that fixed build.
 bool is_fixed5000(const std::vector<int>& rad, int L) {
     return L == 5000 && rad == std::vector<int>(std::begin(sp::kFixed5000Radices), std::end(sp::kFixed5000Radices));
