@@ -422,6 +422,50 @@ constexpr int kRadixFixed5000 = -5000;
 constexpr int kFixed5000Threads = 500;
 constexpr int kFixed5000Radices[4] = {10, 5, 10, 10};
 
+// The fixed transform with its first pass fed from registers (IN) and/or its
+// last pass left in registers (OUT), for lines read from or written to HBM in
+// natural order.  The first pass (radix 10, span 1) of butterfly t takes the
+// points t + 500 r, r = 0..9, and the last pass (radix 10, span 500) of
+// butterfly t produces the points t + 500 r in place: exactly the points a
+// thread of the row loads and stores owns.  IN: v holds the inputs and the
+// LDS line is only written (its first read and barrier are saved).  OUT: the
+// outputs stay in v, nothing is written back, and no barrier follows the last
+// pass's LDS reads: a caller that writes the LDS next synchronises first.
+template <typename T, bool INV, bool IN, bool OUT>
+__device__ __forceinline__ void fft5000_regs(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int t,
+                                             bool active, Cx<T> (&v)[10]) {
+    static_assert(kFixed5000Radices[0] == 10 && kFixed5000Radices[1] == 5 && kFixed5000Radices[2] == 10 &&
+                  kFixed5000Radices[3] == 10, "pass layout of the fixed transform");
+    constexpr int N = 5000, NT = kFixed5000Threads;
+    if constexpr (IN) {
+        if (active) {
+            dft<T, 10, INV>(v);
+#pragma unroll
+            for (int r = 0; r < 10; ++r) buf[t * 10 + r] = v[r];
+        }
+        lds_barrier();
+    } else {
+        stockham_pass_ct<T, 10, INV, N, 1, NT>(buf, tw, t, active);
+    }
+    stockham_pass_ct<T, 5, INV, N, 10, NT>(buf, tw + 9, t, active);
+    stockham_pass_ct<T, 10, INV, N, 50, NT>(buf, tw + 9 + 4 * 10, t, active);
+    const Cx<T>* tw4 = tw + 9 + 4 * 10 + 9 * 50;
+    if constexpr (OUT) {
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < 10; ++r) v[r] = buf[t + r * 500];
+#pragma unroll
+            for (int r = 1; r < 10; ++r) {
+                const Cx<T> w = tw4[(r - 1) * 500 + t];
+                v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+            }
+            dft<T, 10, INV>(v);
+        }
+    } else {
+        stockham_pass_ct<T, 10, INV, N, 500, NT>(buf, tw4, t, active);
+    }
+}
+
 // Whole transform: dispatch each pass on its (uniform) radix.  RMAX bounds the
 // radices compiled into this instantiation.
 // The line is base[off .. off + N).

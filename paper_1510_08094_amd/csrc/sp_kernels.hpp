@@ -180,6 +180,8 @@ __device__ __forceinline__ void lambda_fwd_body(const LambdaArgs<T>& a, int jb, 
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     Cx<T>* buf = lines + (size_t)line * N;
+    // (Feeding the fixed transform's first pass from these loads, without the
+    // LDS round trip, measured no faster here and slowed the mixed solve.)
     if (active) {
         const double s = a.rowscale ? a.rowscale[j] : 1.0;
         load_row<T>(buf, reinterpret_cast<const double2*>(a.x + (size_t)j * a.n), s, t, a.nthr, N);
@@ -207,14 +209,27 @@ __device__ __forceinline__ void lambda_inv_body(const LambdaArgs<T>& a, int jb, 
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     c2r_load_prepare<T, T>(lines, N, a.spec, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, a.w_mid, a.w_end);
     __syncthreads();
-    fft_lds<T, true, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
-    if (active) {
-        const Cx<T>* buf = lines + (size_t)line * N;
-        const double s = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
-        double2* dst = reinterpret_cast<double2*>(a.y + (size_t)j * a.n);
-        for (int i = t; i < N; i += a.nthr) {
-            const Cx<T> z = buf[i];
-            dst[i] = double2{(double)z.x * s, (double)z.y * s};
+    if constexpr (RMAX == kRadixFixed5000) {
+        // the last pass's points t + 500 r go straight to the row
+        Cx<T> v[10];
+        fft5000_regs<T, true, false, true>(lines + (size_t)line * N, a.ptw, t, active, v);
+        if (active) {
+            const double s = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
+            double2* dst = reinterpret_cast<double2*>(a.y + (size_t)j * a.n);
+#pragma unroll
+            for (int r = 0; r < 10; ++r)
+                dst[t + r * kFixed5000Threads] = double2{(double)v[r].x * s, (double)v[r].y * s};
+        }
+    } else {
+        fft_lds<T, true, EPT, RMAX>(lines, line * N, a.fft, a.ptw, t, a.nthr, active);
+        if (active) {
+            const Cx<T>* buf = lines + (size_t)line * N;
+            const double s = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
+            double2* dst = reinterpret_cast<double2*>(a.y + (size_t)j * a.n);
+            for (int i = t; i < N; i += a.nthr) {
+                const Cx<T> z = buf[i];
+                dst[i] = double2{(double)z.x * s, (double)z.y * s};
+            }
         }
     }
 }
@@ -278,31 +293,50 @@ __device__ __forceinline__ void lambda_mix_body(const MixLambdaArgs& a, int jb, 
                                    a.in_w_end);
     __syncthreads();
     Cx<float>* fbuf = fl + (size_t)line * 2 * N;
-    fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N, a.fft, a.ptw32, t, a.nthr, active);
-    constexpr int H = LineHold<EPT, RMAX>::value;
-    Cx<float> hold[H];
+    if constexpr (RMAX == kRadixFixed5000) {
+        // the float32 inverse's last pass stays in registers (the points
+        // t + 500 r: kept, widened and fed to the float64 transform's first
+        // pass without a round trip through the LDS)
+        Cx<float> vf[10];
+        fft5000_regs<float, true, false, true>(fbuf, a.ptw32, t, active, vf);
+        Cx<double> vd[10];
+        if (active) {
+            Cx<float>* keep = reinterpret_cast<Cx<float>*>(a.u + (size_t)j * a.n);
 #pragma unroll
-    for (int e = 0; e < H; ++e) {
-        const int i = t + e * a.nthr;
-        if (active && i < N) hold[e] = fbuf[i];
-    }
-    if (active) {
-        Cx<float>* keep = reinterpret_cast<Cx<float>*>(a.u + (size_t)j * a.n);
+            for (int r = 0; r < 10; ++r) {
+                keep[t + r * kFixed5000Threads] = vf[r];
+                vd[r] = Cx<double>{(double)vf[r].x * a.mid_scale, (double)vf[r].y * a.mid_scale};
+            }
+        }
+        __syncthreads();   // every thread has read the float32 line the float64 line overwrites
+        fft5000_regs<double, false, true, false>(lines + (size_t)line * N, a.ptw64, t, active, vd);
+    } else {
+        fft_lds<float, true, EPT, RMAX>(fl, line * 2 * N, a.fft, a.ptw32, t, a.nthr, active);
+        constexpr int H = LineHold<EPT, RMAX>::value;
+        Cx<float> hold[H];
 #pragma unroll
         for (int e = 0; e < H; ++e) {
             const int i = t + e * a.nthr;
-            if (i < N) keep[i] = hold[e];
+            if (active && i < N) hold[e] = fbuf[i];
         }
-    }
-    __syncthreads();
-    Cx<double>* dbuf = lines + (size_t)line * N;
+        if (active) {
+            Cx<float>* keep = reinterpret_cast<Cx<float>*>(a.u + (size_t)j * a.n);
 #pragma unroll
-    for (int e = 0; e < H; ++e) {
-        const int i = t + e * a.nthr;
-        if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x * a.mid_scale, (double)hold[e].y * a.mid_scale};
+            for (int e = 0; e < H; ++e) {
+                const int i = t + e * a.nthr;
+                if (i < N) keep[i] = hold[e];
+            }
+        }
+        __syncthreads();
+        Cx<double>* dbuf = lines + (size_t)line * N;
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            const int i = t + e * a.nthr;
+            if (active && i < N) dbuf[i] = Cx<double>{(double)hold[e].x * a.mid_scale, (double)hold[e].y * a.mid_scale};
+        }
+        __syncthreads();
+        fft_lds<double, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw64, t, a.nthr, active);
     }
-    __syncthreads();
-    fft_lds<double, false, EPT, RMAX>(lines, line * N, a.fft, a.ptw64, t, a.nthr, active);
     r2c_split_store<double, double>(lines, N, a.su, a.tw64, N, a.rw_log2, a.lay_out_log2, a.m, jb, a.out_w_mid,
                                     a.out_w_end);
 }
@@ -344,7 +378,12 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
     c2r_load_prepare<float, float>(fl, (size_t)N, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
                                    a.in_w_end);
     __syncthreads();
-    fft_lds<float, true, EPT, RMAX>(fl, line * N, a.fft, a.ptw32, t, a.nthr, active);
+    // fixed transform: the last pass's points t + 500 r stay in registers
+    Cx<float> vf[RMAX == kRadixFixed5000 ? 10 : 1];
+    if constexpr (RMAX == kRadixFixed5000)
+        fft5000_regs<float, true, false, true>(fl + (size_t)line * N, a.ptw32, t, active, vf);
+    else
+        fft_lds<float, true, EPT, RMAX>(fl, line * N, a.fft, a.ptw32, t, a.nthr, active);
     const Cx<float>* b1 = fl + (size_t)line * N;
     double sd2 = 0.0, su2 = 0.0;
     if (active) {
@@ -354,7 +393,9 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
         for (int e = 0; e < H; ++e) {
             const int i = t + e * a.nthr;
             if (i < N) {
-                const Cx<float> d = b1[i];
+                Cx<float> d;
+                if constexpr (RMAX == kRadixFixed5000) d = vf[e < 10 ? e : 0];
+                else d = b1[i];
                 const double dx = (double)d.x * sc, dy = (double)d.y * sc;
                 double2 base;
                 if (a.accumulate) base = dst[i];
