@@ -151,12 +151,13 @@ __device__ __forceinline__ void c2r_load_prepare(Cx<T>* lines, size_t stride, co
 }
 
 // x_{2i}, x_{2i+1} (one double2 per complex input) times s into buf[i] for
-// i = t, t + nthr, ... < N, eight loads in flight per thread (branch-free:
-// the last one is re-read).
+// i = t, t + nthr, ... < N, ten loads in flight per thread (branch-free:
+// the last one is re-read): the whole row of the length-5000 transform in one
+// round trip (eight measured 4% slower there).
 template <typename T>
 __device__ __forceinline__ void load_row(Cx<T>* buf, const double2* __restrict__ src, double s, int t, int nthr,
                                          int N) {
-    constexpr int kB = 8;
+    constexpr int kB = 10;
     const int cnt = t < N ? (N - 1 - t) / nthr + 1 : 0;
     for (int e0 = 0; e0 < cnt; e0 += kB) {
         double2 v[kB];

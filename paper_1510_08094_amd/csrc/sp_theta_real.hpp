@@ -131,7 +131,7 @@ template <typename T, typename TS>
 __device__ __forceinline__ double load_part(T* y, const Cx<TS>* __restrict__ spec, int part, int k, int m,
                                             int N, int lay, bool sine, const double* __restrict__ fint_w,
                                             int tid, int nthr) {
-    constexpr int kBatch = 8;   // loads in flight per thread
+    constexpr int kBatch = 8;   // loads in flight per thread (24, all of them at m = 10^4, measured slower)
     const TS* sp = reinterpret_cast<const TS*>(spec) + part + 2 * spec_at(tid, k, N, lay);
     const size_t dj = (size_t)2 * (((size_t)(nthr >> lay) * (N + 1)) << lay);
     const bool odd = (tid & 1) != 0;
