@@ -60,8 +60,18 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
     c2r_load_prepare<double, double>(lines + N, stride, a.spec_t, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
                                      1.0);
     __syncthreads();
-    fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N, a.fft, a.ptw, t, a.nthr, active);
-    fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N + N, a.fft, a.ptw, t, a.nthr, active);
+    // length-5000 transform: both last passes stay in registers (the points
+    // t + 500 e the output loop takes; the two lines are disjoint, so the
+    // second transform may write while the first one's last reads run)
+    constexpr bool REGS = RMAX == kRadixFixed5000;
+    Cx<double> v1[REGS ? 10 : 1], v2[REGS ? 10 : 1];
+    if constexpr (REGS) {
+        fft5000_regs<double, true, false, true>(lines + (size_t)line * stride, a.ptw, t, active, v1);
+        fft5000_regs<double, true, false, true>(lines + (size_t)line * stride + N, a.ptw, t, active, v2);
+    } else {
+        fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N, a.fft, a.ptw, t, a.nthr, active);
+        fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N + N, a.fft, a.ptw, t, a.nthr, active);
+    }
     if (active) {
         const Cx<double>* fl = lines + (size_t)line * stride;   // samples 2i, 2i+1 of (d f/d lambda) / sin(theta)
         const Cx<double>* ft = fl + N;                            // and of d f/d theta
@@ -73,8 +83,20 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
         double2* oz = a.gz ? reinterpret_cast<double2*>(a.gz + (size_t)j * a.n) : nullptr;
         const bool acc = a.accumulate != 0;
         const int nout = a.nout;
-        for (int i = t; i < N; i += a.nthr) {
-            const Cx<double> dl = fl[i], dt = ft[i];
+        // (REGS: exactly ten points per thread, i = t + 500 e, a loop of fixed count)
+        constexpr int EMAX = REGS ? 10 : 1 << 30;
+#pragma unroll(REGS ? 10 : 1)
+        for (int e = 0; e < EMAX; ++e) {
+            const int i = t + e * a.nthr;
+            if (!REGS && i >= N) break;
+            Cx<double> dl, dt;
+            if constexpr (REGS) {
+                dl = v1[e];
+                dt = v2[e];
+            } else {
+                dl = fl[i];
+                dt = ft[i];
+            }
             const double2 s = sl[i], c = cl[i];
             double r[3][2];   // the three outputs at samples 2i, 2i+1
 #pragma unroll
@@ -107,8 +129,11 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
     }
 }
 
+// The length-5000 build runs one row per workgroup (two float64 lines fill
+// the LDS), 512 threads: its bound leaves room for both transforms' last
+// passes in registers.
 template <int EPT, int RMAX>
-__global__ void __launch_bounds__(1024) k_lambda_grad(GradArgs a) {
+__global__ void __launch_bounds__(RMAX == kRadixFixed5000 ? 512 : 1024) k_lambda_grad(GradArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
     if (jb << a.rw_log2 >= a.m) return;
