@@ -350,18 +350,83 @@ __global__ void __launch_bounds__(1024) k_lambda_mix(MixLambdaArgs a) {
     lambda_mix_body<EPT, RMAX>(a, jb, smem_raw);
 }
 
+// Per-block sums of (s d)^2 and u^2 of the update pass (when a.partial is set).
+__device__ __forceinline__ void block_partials(const MixLambdaArgs& a, int jb, double sd2, double su2,
+                                               double (*red)[16]) {
+    if (!a.partial) return;
+    for (int off = 32; off > 0; off >>= 1) {
+        sd2 += __shfl_down(sd2, off, 64);
+        su2 += __shfl_down(su2, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wave] = sd2; red[1][wave] = su2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { x += red[0][w]; y += red[1][w]; }
+        a.partial[2 * jb] = x;
+        a.partial[2 * jb + 1] = y;
+    }
+    __syncthreads();
+}
+
 // u = s (u0 + d) (or u += s d) with u0, d the float32 inverse DFTs of the
 // weighted s0 and sd, summed in float64, s = out_scale * rowscale[j].  u0 is
 // the copy the mix pass left at the start of each output row; every thread
-// reads the values it combines into registers before the first barrier, so
-// no row is overwritten before it has been read.  LDS per row: N float32
-// complex (the correction line only).
+// reads the values it combines into registers before a full barrier that
+// precedes the row's first store, so no row is overwritten before it has
+// been read.  LDS per row: N float32 complex (the correction line only).
 // Optionally accumulates per-block sums of (s d)^2 and u^2.
+// The fixed length-5000 transform runs the rows of a tile (at most two: two
+// float64 rows fill the LDS in the other lambda passes) one after the other
+// in the threads of one row, so that the tile takes 512 threads and two
+// tiles share a compute unit; the general form runs the rows side by side.
 template <int EPT, int RMAX>
 __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int jb, unsigned char* smem_raw,
                                                    double (*red)[16]) {
     Cx<float>* fl = reinterpret_cast<Cx<float>*>(smem_raw);   // row r: the correction line
     const int N = a.N;
+    if constexpr (RMAX == kRadixFixed5000) {
+        c2r_load_prepare<float, float>(fl, (size_t)N, a.sd, a.tw32, N, a.rw_log2, a.lay_log2, a.m, jb, a.in_w_mid,
+                                       a.in_w_end);
+        __syncthreads();
+        double sd2 = 0.0, su2 = 0.0;
+#pragma unroll 1
+        for (int row = 0; row < (1 << a.rw_log2); ++row) {
+            int t = threadIdx.x;
+            asm volatile("" : "+v"(t));   // keeps each row's index arithmetic inside the row (no spills)
+            const int j = (jb << a.rw_log2) + row;
+            const bool act = t < kFixed5000Threads && j < a.m;
+            // the last pass's points t + 500 r stay in registers
+            Cx<float> vf[10];
+            fft5000_regs<float, true, false, true>(fl + (size_t)row * N, a.ptw32, t, act, vf);
+            Cx<float> u0[10];
+            if (!a.accumulate && act) {
+                const Cx<float>* keep = reinterpret_cast<const Cx<float>*>(a.u + (size_t)j * a.n);
+#pragma unroll
+                for (int r = 0; r < 10; ++r) u0[r] = keep[t + r * kFixed5000Threads];
+            }
+            __syncthreads();   // every thread holds its kept values of row j before any thread writes the row
+            if (act) {
+                const double sc = a.out_scale * (a.rowscale ? a.rowscale[j] : 1.0);
+                double2* dst = reinterpret_cast<double2*>(a.u + (size_t)j * a.n);
+#pragma unroll
+                for (int r = 0; r < 10; ++r) {
+                    const int i = t + r * kFixed5000Threads;
+                    const double dx = (double)vf[r].x * sc, dy = (double)vf[r].y * sc;
+                    double2 base;
+                    if (a.accumulate) base = dst[i];
+                    else base = double2{(double)u0[r].x * sc, (double)u0[r].y * sc};
+                    const double2 v = double2{base.x + dx, base.y + dy};
+                    dst[i] = v;
+                    sd2 += dx * dx + dy * dy;
+                    su2 += v.x * v.x + v.y * v.y;
+                }
+            }
+        }
+        block_partials(a, jb, sd2, su2, red);
+        return;
+    }
     const int line = threadIdx.x / a.nthr;
     const int t = threadIdx.x - line * a.nthr;
     const int j = (jb << a.rw_log2) + line;
@@ -408,22 +473,7 @@ __device__ __forceinline__ void lambda_update_body(const MixLambdaArgs& a, int j
             }
         }
     }
-    if (a.partial) {
-        for (int off = 32; off > 0; off >>= 1) {
-            sd2 += __shfl_down(sd2, off, 64);
-            su2 += __shfl_down(su2, off, 64);
-        }
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0) { red[0][wave] = sd2; red[1][wave] = su2; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double x = 0.0, y = 0.0;
-            for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { x += red[0][w]; y += red[1][w]; }
-            a.partial[2 * jb] = x;
-            a.partial[2 * jb + 1] = y;
-        }
-        __syncthreads();
-    }
+    block_partials(a, jb, sd2, su2, red);
 }
 
 template <int EPT, int RMAX>

@@ -250,6 +250,7 @@ struct sp_plan_s {
     bool theta_real = false;  // even m: one real part per theta workgroup, DFT length m/2
     int theta_grid = 0;       // theta workgroups
     size_t lam_lds = 0, theta_lds64 = 0, theta_lds32 = 0;
+    int upd_block = 0;        // threads of the mixed update pass
     int k8 = 0;
     FftDesc fft_lam{}, fft_theta{};
     KernelSet<double> kd{};
@@ -617,6 +618,8 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
             if (fn) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->theta_lds64);
     for (const void* fn : {(const void*)p->km.mix, (const void*)p->km.update})
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lam_lds);
+    // the fixed transform's update pass runs a tile's rows one after the other in one row's threads
+    p->upd_block = round_up((rs_lam == sp::kRadixFixed5000 ? 1 : 1 << p->rw_log2) * p->lam_threads, 64);
     // forward lambda passes: when a tile of the plan's rows fills the LDS so that one workgroup
     // runs per compute unit, the forward pass takes half the rows (measured at n = m = 10^4:
     // 0.53 -> 0.47 ms); the passes that read a spectrum keep the full tile, whose reads take
@@ -1320,7 +1323,7 @@ int run_mixed(sp_plan p, const double* f, double* u, double c0, bool adjoint, hi
             {
                 ProfScope ps(p, SP_KERNEL_LAMBDA_UPD, s);
                 // float32 correction lines only: half the LDS of the other lambda passes
-                hipLaunchKernelGGL(p->km.update, lam_grid, lam_block, p->lam_lds / 2, s, ma);
+                hipLaunchKernelGGL(p->km.update, lam_grid, dim3(p->upd_block), p->lam_lds / 2, s, ma);
             }
             // correction norms of the last two corrections: [1..2] last, [5..6] the one before
             if (want && it >= R - 1) {
