@@ -55,20 +55,26 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
     const int j = (jb << a.rw_log2) + line;
     const bool active = line < (1 << a.rw_log2) && j < a.m;
     const size_t stride = 2 * (size_t)N;
-    c2r_load_prepare<double, double, true>(lines, stride, a.spec_q, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
-                                           1.0);
-    c2r_load_prepare<double, double>(lines + N, stride, a.spec_t, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
-                                     1.0);
-    __syncthreads();
-    // length-5000 transform: both last passes stay in registers (the points
-    // t + 500 e the output loop takes; the two lines are disjoint, so the
-    // second transform may write while the first one's last reads run)
+    // length-5000 transform (one row per workgroup): one float64 line, the
+    // two inverse transforms in turn, each leaving its last pass in registers
+    // (the points t + 500 e the output loop takes), so that two workgroups
+    // share a compute unit
     constexpr bool REGS = RMAX == kRadixFixed5000;
     Cx<double> v1[REGS ? 10 : 1], v2[REGS ? 10 : 1];
     if constexpr (REGS) {
-        fft5000_regs<double, true, false, true>(lines + (size_t)line * stride, a.ptw, t, active, v1);
-        fft5000_regs<double, true, false, true>(lines + (size_t)line * stride + N, a.ptw, t, active, v2);
+        c2r_load_prepare<double, double, true>(lines, N, a.spec_q, a.tw, N, 0, a.lay_log2, a.m, jb, 1.0, 1.0);
+        __syncthreads();
+        fft5000_regs<double, true, false, true>(lines, a.ptw, t, active, v1);
+        __syncthreads();   // every thread has read the line's last pass
+        c2r_load_prepare<double, double>(lines, N, a.spec_t, a.tw, N, 0, a.lay_log2, a.m, jb, 1.0, 1.0);
+        __syncthreads();
+        fft5000_regs<double, true, false, true>(lines, a.ptw, t, active, v2);
     } else {
+        c2r_load_prepare<double, double, true>(lines, stride, a.spec_q, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb,
+                                               1.0, 1.0);
+        c2r_load_prepare<double, double>(lines + N, stride, a.spec_t, a.tw, N, a.rw_log2, a.lay_log2, a.m, jb, 1.0,
+                                         1.0);
+        __syncthreads();
         fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N, a.fft, a.ptw, t, a.nthr, active);
         fft_lds<double, true, EPT, RMAX>(lines, line * 2 * N + N, a.fft, a.ptw, t, a.nthr, active);
     }
@@ -129,11 +135,12 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
     }
 }
 
-// The length-5000 build runs one row per workgroup (two float64 lines fill
-// the LDS), 512 threads: its bound leaves room for both transforms' last
-// passes in registers.
+// The length-5000 build runs one row per workgroup in 512 threads and one
+// float64 line: its bound (128 registers) lets two workgroups share a
+// compute unit.
 template <int EPT, int RMAX>
-__global__ void __launch_bounds__(RMAX == kRadixFixed5000 ? 512 : 1024) k_lambda_grad(GradArgs a) {
+__global__ void __launch_bounds__(RMAX == kRadixFixed5000 ? 512 : 1024, RMAX == kRadixFixed5000 ? 4 : 1)
+    k_lambda_grad(GradArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int jb = lambda_tile(a.lay_log2 - a.rw_log2);
     if (jb << a.rw_log2 >= a.m) return;

@@ -632,11 +632,13 @@ int plan_create(const sp_desc* d, hipStream_t stream, const Sched& sc, sp_plan* 
         p->fwd_grid = round_up(nblk, 8 << (p->lay_log2 - p->fwd_rw_log2));
     }
     // gradient pass: two float64 lines per row, as many rows per workgroup as fit (at most the plan's);
+    // the fixed transform's build takes one row and one line (its two transforms run in turn);
     // the theta division by sin(theta) needs one thread per chunk of each parity class
     const int div_hold = p->theta_real ? sp::kRealLoadHold : sp::kThetaHold;
     const int div_threads = ceil_div((m + 1) / 2, div_hold) + ceil_div(m / 2, div_hold);
-    for (int g = p->rw_log2; g >= 0 && div_threads <= p->theta_threads; --g) {
-        const size_t lds = ((size_t)2 * N << g) * sizeof(Cx<double>);
+    const bool grad_one_line = rs_lam == sp::kRadixFixed5000;
+    for (int g = grad_one_line ? 0 : p->rw_log2; g >= 0 && div_threads <= p->theta_threads; --g) {
+        const size_t lds = ((size_t)(grad_one_line ? 1 : 2) * N << g) * sizeof(Cx<double>);
         if (lds + static_lds <= lds_limit) {
             p->grad = grad_kernel(rs_lam);
             p->grad_rw_log2 = g;
