@@ -91,7 +91,8 @@ __device__ __forceinline__ void lambda_grad_body(const GradArgs& a, int jb, unsi
         const int nout = a.nout;
         // (REGS: exactly ten points per thread, i = t + 500 e, a loop of fixed count)
         constexpr int EMAX = REGS ? 10 : 1 << 30;
-#pragma unroll(REGS ? 10 : 1)
+        constexpr int kUnroll = REGS ? 10 : 1;
+#pragma unroll kUnroll
         for (int e = 0; e < EMAX; ++e) {
             const int i = t + e * a.nthr;
             if (!REGS && i >= N) break;
