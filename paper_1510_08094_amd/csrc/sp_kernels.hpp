@@ -5,10 +5,13 @@
 // Spectrum layout in HBM ("j-blocked"): the half spectrum X_k(theta_j),
 // k = 0..N (N = n/2), is stored as spec[((j / RL) * (N + 1) + k) * RL + j % RL]
 // with RL = 2^lay a power of two, the run length.  Each buffer takes the
-// layout its reader prefers: spectra read by a theta pass use runs of 8 rows
-// (one 128-byte line of a wavenumber in float64; a lambda workgroup owns
-// RW <= RL rows and writes its part of every run), spectra read by a lambda
-// pass use RL = RW (one contiguous block per lambda workgroup).
+// layout its reader prefers: spectra read by a theta pass use runs of at
+// least 8 rows (one 128-byte line of a wavenumber in float64; a lambda
+// workgroup owns RW <= RL rows and writes its part of every run).  The float64
+// solve's theta output, read by the lambda inverse, uses RL = RW (one
+// contiguous block per lambda workgroup); the mixed solve's float32 spectra
+// and every spectrum of a batch keep the theta runs, since the theta passes
+// write them in halves (one real part per workgroup).
 #pragma once
 #include "sp_fft.hpp"
 

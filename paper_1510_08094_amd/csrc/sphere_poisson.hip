@@ -1866,7 +1866,10 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
     for (int r = 0; r < count; ++r) {
         const int rw = 1 << rwl[r];
         nblk[r] = (m[r] + rw - 1) / rw;
-        const size_t elems = (size_t)nblk[r] * (n[r] / 2 + 1) * rw;
+        // spectrum runs of at least 8 rows (a 128-byte line per wavenumber in
+        // float64), as in a single plan: the theta tiles' column reads need them
+        const int rl = 1 << std::max(rwl[r], kLayLog2);
+        const size_t elems = (size_t)((m[r] + rl - 1) / rl) * (n[r] / 2 + 1) * rl;
         o64[r] = take(elems * sizeof(Cx<double>));
         if (mixed) {
             oB[r] = take(elems * sizeof(Cx<double>));
@@ -1937,7 +1940,7 @@ int build_batch(int count, const int* n, const int* m, const double* const* f, d
         const SizeTables& L = lam[lkey[r]];
         const SizeTables& T = th[tkey[r]];
         sp::RhsDesc& d = descs[r];
-        d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r]; d.lay_log2 = rwl[r];
+        d.n = n[r]; d.m = m[r]; d.N = n[r] / 2; d.rw_log2 = rwl[r]; d.lay_log2 = std::max(rwl[r], kLayLog2);
         d.lam_nthr = lnt[r]; d.theta_nthr_fft = tft[r]; d.theta_real = treal[r] ? 1 : 0;
         d.k64 = std::max(16, m[r] / 64);
         d.c0 = 0.0;
