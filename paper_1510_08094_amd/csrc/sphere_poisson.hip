@@ -394,7 +394,9 @@ bool lambda_schedule(int N, int m, const std::vector<int>& rad, size_t lds_limit
         if ((size_t)rw * N * sizeof(Cx<double>) > lds_limit) break;
         best = l;
         if (rw >= m) break;
-        if (rw * t >= 256 && rw * (int)sizeof(Cx<double>) >= 128) break;
+        // enough threads; rows of short transforms stop there (more tiles per CU),
+        // rows of long ones also fill a 128-byte spectrum run
+        if (rw * t >= 256 && (t < 256 || rw * (int)sizeof(Cx<double>) >= 128)) break;
     }
     if (best < 0) return false;
     *rw_log2 = best;
